@@ -1,0 +1,152 @@
+"""Plain FP64 CPU EmbedSOM oracle -- TEST INFRASTRUCTURE ONLY.
+
+The arithmetic lives in ``esom_oracle.c`` (plain C, double precision, direct
+differences, sorted insertion, Cramer's rule).  This module only compiles it
+with gcc and marshals numpy arrays through ctypes.
+
+Only ``tests/``, ``__graft_entry__.smoke()`` and the CPU-baseline leg of
+``bench.py`` may import this package.  The GPU library never does, and this
+package never imports the GPU library.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import subprocess
+
+import numpy as np
+
+_HERE = os.path.dirname(os.path.abspath(__file__))
+_SRC = os.path.join(_HERE, "esom_oracle.c")
+_LIB = os.path.join(_HERE, "liboracle.so")
+_lib = None
+
+DEFAULT_BOOST = 1.0
+DEFAULT_ADJUST = 1.0
+DEFAULT_CUTOFF = 10.0
+DEFAULT_GRAVITY = 1e-5
+
+
+def build(force: bool = True) -> str:
+    """Compile the oracle with gcc (no FMA contraction, no fast-math)."""
+    if force or not os.path.exists(_LIB):
+        tmp = _LIB + ".tmp%d" % os.getpid()
+        cmd = ["gcc", "-O2", "-std=c99", "-ffp-contract=off", "-fPIC", "-shared",
+               "-pthread", "-o", tmp, _SRC, "-lm"]
+        subprocess.check_call(cmd)
+        os.replace(tmp, _LIB)
+    return _LIB
+
+
+def _load():
+    global _lib
+    if _lib is None:
+        if not os.path.exists(_LIB):
+            build()
+        lib = ctypes.CDLL(_LIB)
+        f32p = ctypes.POINTER(ctypes.c_float)
+        f64p = ctypes.POINTER(ctypes.c_double)
+        i32p = ctypes.POINTER(ctypes.c_int32)
+        i64p = ctypes.POINTER(ctypes.c_int64)
+        i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        lib.oracle_scores.argtypes = [f64p, i32, i32, dbl, dbl, f64p]
+        lib.oracle_scores.restype = i32
+        lib.oracle_knn.argtypes = [f32p, i64, i32, i64, f32p, i32, i32, i32p, f64p, i32]
+        lib.oracle_knn.restype = i32
+        lib.oracle_embed.argtypes = [f32p, i64, i32, i64, f32p, f32p, i32, i32, dbl, dbl,
+                                     dbl, dbl, f64p, i32p, f64p, i64p, i32]
+        lib.oracle_embed.restype = i32
+        lib.oracle_landmark_update.argtypes = [f32p, i64, i32, i64, f32p, f32p, i32, i32,
+                                               dbl, dbl, f64p, i64p, i32]
+        lib.oracle_landmark_update.restype = i32
+        _lib = lib
+    return _lib
+
+
+def _ptr(a, ctype):
+    return a.ctypes.data_as(ctypes.POINTER(ctype))
+
+
+def _f32_rows(X):
+    X = np.asarray(X)
+    if X.dtype != np.float32:
+        raise TypeError("oracle inputs must already be float32 (the GPU's inputs)")
+    if X.ndim != 2:
+        raise ValueError("expected a 2-D float32 array")
+    if X.strides[1] != 4 or X.strides[0] % 4 or X.strides[0] < 4 * X.shape[1]:
+        X = np.ascontiguousarray(X)
+    return X, X.strides[0] // 4
+
+
+def scores(delta, g, boost=DEFAULT_BOOST, cutoff=DEFAULT_CUTOFF):
+    """Scores of sorted neighbour distances (Euclidean).  Returns (s, degenerate)."""
+    lib = _load()
+    d = np.ascontiguousarray(delta, dtype=np.float64)
+    s = np.zeros_like(d)
+    rc = lib.oracle_scores(_ptr(d, ctypes.c_double), len(d), int(g), float(boost),
+                           float(cutoff), _ptr(s, ctypes.c_double))
+    if rc < 0:
+        raise ValueError("oracle_scores: invalid arguments")
+    return s, bool(rc == 1)
+
+
+def knn(X, L, m, threads=1):
+    """The m nearest landmarks of every row of X: (idx int32 n x m, d2 float64 n x m)."""
+    lib = _load()
+    X, ldx = _f32_rows(X)
+    L = np.ascontiguousarray(L, dtype=np.float32)
+    n, d = X.shape
+    g = L.shape[0]
+    idx = np.empty((n, m), np.int32)
+    d2 = np.empty((n, m), np.float64)
+    rc = lib.oracle_knn(_ptr(X, ctypes.c_float), n, d, ldx, _ptr(L, ctypes.c_float), g, m,
+                        _ptr(idx, ctypes.c_int32), _ptr(d2, ctypes.c_double), threads)
+    if rc != 0:
+        raise ValueError("oracle_knn failed (%d)" % rc)
+    return idx, d2
+
+
+def embed(X, L, l, k, boost=DEFAULT_BOOST, adjust=DEFAULT_ADJUST, cutoff=DEFAULT_CUTOFF,
+          gravity=DEFAULT_GRAVITY, threads=1):
+    """EmbedSOM projection.  Returns dict(out n x 2 f64, idx n x (k+1), d2 n x (k+1),
+    n_degenerate)."""
+    lib = _load()
+    X, ldx = _f32_rows(X)
+    L = np.ascontiguousarray(L, dtype=np.float32)
+    l = np.ascontiguousarray(l, dtype=np.float32)
+    n, d = X.shape
+    g = L.shape[0]
+    if L.shape[1] != d or l.shape != (g, 2):
+        raise ValueError("shape mismatch")
+    out = np.empty((n, 2), np.float64)
+    idx = np.empty((n, k + 1), np.int32)
+    d2 = np.empty((n, k + 1), np.float64)
+    ndeg = ctypes.c_int64(0)
+    rc = lib.oracle_embed(_ptr(X, ctypes.c_float), n, d, ldx, _ptr(L, ctypes.c_float),
+                          _ptr(l, ctypes.c_float), g, int(k), float(boost), float(adjust),
+                          float(cutoff), float(gravity), _ptr(out, ctypes.c_double),
+                          _ptr(idx, ctypes.c_int32), _ptr(d2, ctypes.c_double),
+                          ctypes.byref(ndeg), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_embed failed (%d)" % rc)
+    return {"out": out, "idx": idx, "d2": d2, "n_degenerate": int(ndeg.value)}
+
+
+def landmark_update(X, L, l, kind, alpha, sigma=0.0, threads=1):
+    """One batch landmark step (kind 'kmeans' or 'som').  Returns (L_new f64, counts)."""
+    lib = _load()
+    X, ldx = _f32_rows(X)
+    L = np.ascontiguousarray(L, dtype=np.float32)
+    l = np.ascontiguousarray(l, dtype=np.float32)
+    n, d = X.shape
+    g = L.shape[0]
+    kid = {"kmeans": 0, "som": 1}[kind]
+    Lout = np.empty((g, d), np.float64)
+    counts = np.empty(g, np.int64)
+    rc = lib.oracle_landmark_update(_ptr(X, ctypes.c_float), n, d, ldx,
+                                    _ptr(L, ctypes.c_float), _ptr(l, ctypes.c_float), g, kid,
+                                    float(alpha), float(sigma), _ptr(Lout, ctypes.c_double),
+                                    _ptr(counts, ctypes.c_int64), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_landmark_update failed (%d)" % rc)
+    return Lout, counts

@@ -1,0 +1,177 @@
+/*
+ * esom.h -- C ABI of libesom, EmbedSOM projection on AMD MI355X (gfx950).
+ *
+ * EmbedSOM (paper: "Scalable semi-supervised dimensionality reduction with
+ * GPU-accelerated EmbedSOM", Section "Landmark-directed dimensionality
+ * reduction") maps every high-dimensional point X_i (n x d) to a 2-D point
+ * x_i (n x 2) using g landmarks with high-dimensional positions L (g x d) and
+ * 2-D positions l (g x 2):
+ *   1. find the k nearest landmarks of X_i (3 <= k <= g, Euclidean);
+ *   2. give them smooth rank-ordered scores s (highest for the closest, zero
+ *      for the k-th when k < g);
+ *   3. for every pair (u,v) of neighbours, project X_i on the line through
+ *      L_u (coordinate 0) and L_v (coordinate 1), giving D_uv;
+ *   4. x_i = argmin_p sum s_u s_v (D_uv - d_uv(p))^2, where d_uv is the same
+ *      affine coordinate in 2-D; a 2x2 linear system solved by Cramer's rule
+ *      (Section "Projection step").
+ *
+ * Conventions for every call:
+ *   - Array arguments are caller-owned.  Calls marked "device" take device
+ *     pointers (e.g. from a torch tensor's data_ptr()); the library never
+ *     frees them and keeps no reference after the work it enqueued finishes.
+ *   - Device work is enqueued on `stream` (a hipStream_t; NULL = the default
+ *     stream) and the call returns before it completes, unless stated.
+ *   - Return value: ESOM_OK (0) or a negative ESOM_E* code.  Argument errors
+ *     are detected synchronously and enqueue nothing.  esom_last_error()
+ *     returns a thread-local message for the last failing call on the calling
+ *     thread (valid until that thread's next call).
+ *   - Inputs must be finite; NaN/Inf point values are not checked and give
+ *     unspecified (but memory-safe) results for those points.
+ *   - One context may be used from several host threads only if its calls
+ *     are serialised by the caller; calls on one context share its scratch
+ *     memory, so two esom_embed calls on one context must not run
+ *     concurrently on different streams.  The serving API below manages its
+ *     own per-slot scratch and may be used concurrently.
+ */
+#ifndef ESOM_H
+#define ESOM_H
+
+#include <stddef.h>
+#include <stdint.h>
+
+#ifdef __cplusplus
+extern "C" {
+#endif
+
+#define ESOM_OK 0
+#define ESOM_EINVAL (-1)    /* invalid argument (shape, parameter, pointer) */
+#define ESOM_ENOMEM (-2)    /* device memory: allocation failed or over budget */
+#define ESOM_EDEVICE (-3)   /* a HIP runtime call failed */
+#define ESOM_EBUSY (-4)     /* serving queue full */
+#define ESOM_ETIMEOUT (-5)  /* wait timed out; the request is still pending */
+#define ESOM_ENOTFOUND (-6) /* unknown dataset or request id */
+
+/* Limits of this build. */
+#define ESOM_MAX_D 256   /* high-dimensional point dimension */
+#define ESOM_MAX_K 64    /* neighbours */
+#define ESOM_MAX_G 8192  /* landmarks */
+
+typedef struct esom_ctx esom_ctx;
+
+/* Distance pass precision.  Both modes return the exact k-nearest sets (ties
+ * broken by landmark index) and the same projection; they differ in how the
+ * candidate landmarks are screened:
+ *   FP32:          FP32 MFMA distance screen, exact FP32 rescore of candidates;
+ *   BF16_RESCORE:  BF16 MFMA screen (FP32 accumulate), exact FP32 rescore of
+ *                  at least 2k candidates, certified against a rigorous BF16
+ *                  error bound; uncertified points are recomputed exactly. */
+typedef enum { ESOM_MODE_FP32 = 0, ESOM_MODE_BF16_RESCORE = 1 } esom_mode;
+
+typedef struct {
+    int32_t k;          /* neighbours, 3 <= k <= g and k <= ESOM_MAX_K */
+    float boost;        /* score sharpness beta > 0 ("smoothing"; default 1) */
+    float adjust;       /* pair weight exponent a: pair (u,v) is weighted
+                           s_u s_v |l_v - l_u|^(2-2a); a = 1 (default) is the
+                           paper's objective */
+    float cutoff;       /* steepness A > 0 of the factor 1-exp(A(delta/delta_k-1))
+                           that zeroes the k-th score when k < g (default 10) */
+    float gravity;      /* eps >= 0: adds eps*sum_i s_i|p-l_{n_i}|^2 so the 2x2
+                           system is never singular (default 1e-5) */
+    int32_t mode;       /* esom_mode */
+    int32_t candidates; /* screen target C (candidates >= C are rescored);
+                           0 = default (k+2 in FP32 mode, 2k in BF16 mode) */
+} esom_params;
+
+/* Counters accumulated by a context since creation or the last reset. */
+typedef struct {
+    int64_t n_points;      /* points embedded */
+    int64_t n_fallback;    /* points recomputed by the exact FP64 path */
+    int64_t n_uncertified; /* ...because the screen certificate failed */
+    int64_t n_near_tie;    /* ...because the k-th and (k+1)-th distances are
+                              closer than FP32 can order */
+    int64_t n_illcond;     /* ...because the 2x2 system is ill-conditioned or a
+                              landmark pair is nearly duplicate */
+    int64_t n_degenerate;  /* ...because all k distances are equal or all scores
+                              vanish (centroid of the neighbours' 2-D positions) */
+    int64_t n_candidates;  /* total screened candidates rescored */
+    int64_t n_slowpath;    /* points sent whole to the exact path because the
+                              shape is outside the fast kernels (k > 32, d above
+                              the mode's fast limit, or g > 4096) */
+    int64_t n_timed;       /* embed calls timed (see esom_set_timing) */
+    double ms_prep;        /* summed device time of landmark preparation */
+    double ms_main;        /* summed device time of the fused embed kernel */
+    double ms_exact;       /* summed device time of the exact FP64 path */
+} esom_stats;
+
+/* Fills *p with the defaults (k = 16, boost 1, adjust 1, cutoff 10,
+ * gravity 1e-5, FP32 mode, default candidates). */
+void esom_default_params(esom_params *p);
+
+/* Creates a context on HIP device `device`.  hbm_budget_bytes bounds the
+ * device memory the context may hold (0 = no bound besides the device). */
+int esom_create(int device, size_t hbm_budget_bytes, esom_ctx **out);
+
+/* Waits for the context's outstanding work and frees everything it owns. */
+void esom_destroy(esom_ctx *ctx);
+
+/* Thread-local description of the last error on this thread ("" if none). */
+const char *esom_last_error(void);
+
+/* EmbedSOM projection (the four steps above) of n points.
+ *   X        device, n rows of d floats, row stride ldx >= d floats, 4-byte aligned
+ *   L_hd     device, g x d floats, row-major, contiguous
+ *   L_2d     device, g x 2 floats, row-major, contiguous
+ *   out      device, n x 2 floats (written)
+ *   knn_idx  device, n x k int32 or NULL: the k nearest landmark indices, sorted
+ *            by (distance, index)
+ *   knn_dist2 device, n x k floats or NULL: their squared distances (FP32)
+ * n == 0 is a no-op.  Errors: ESOM_EINVAL for k < 3, k > g, k > ESOM_MAX_K,
+ * d < 1 or > ESOM_MAX_D, g > ESOM_MAX_G, n < 0, ldx < d, NULL or misaligned
+ * pointers, boost <= 0, boost*sqrt(H_k) >= 80 (H_k the k-th harmonic number:
+ * the largest score exponent), cutoff <= 0, gravity < 0, non-finite adjust,
+ * unknown mode, candidates outside [0, g]; ESOM_ENOMEM if the scratch memory
+ * does not fit the budget; ESOM_EDEVICE if a launch fails. */
+int esom_embed(esom_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+               const float *L_hd, const float *L_2d, int32_t g, const esom_params *params,
+               float *out, int32_t *knn_idx, float *knn_dist2, void *stream);
+
+/* One semi-supervised landmark step (Section "User supervision and model
+ * interaction": an interactive k-means with a low learning rate in graph
+ * mode, a SOM trained on the user's 2-D topology in SOM mode), batch form:
+ *   b(i) = nearest landmark of X_i; S_j, c_j = sum and count of the points
+ *   with b(i) = j;
+ *   kind 0 (k-means): L_j += alpha (S_j / c_j - L_j) if c_j > 0;
+ *   kind 1 (SOM):     L_j += alpha (sum_b h_jb S_b / sum_b h_jb c_b - L_j) if
+ *                     the denominator is positive, h_jb = exp(-|l_j-l_b|^2 /
+ *                     (2 sigma^2)) (sigma = 0: h_jb = [j == b]).
+ *   L_hd     device, g x d floats, updated in place (stream-ordered)
+ *   L_2d     device, g x 2 floats (read; may be NULL for kind 0)
+ *   nearest  device, n int32 or NULL: b(i) from a previous esom_embed (its
+ *            knn_idx[:, 0]); NULL = computed here exactly
+ *   counts   device, g int32 or NULL: receives c_j
+ * Sums and counts are accumulated in FP64, so the result does not depend on
+ * the order in which points are visited beyond the final FP32 rounding.
+ * Errors: ESOM_EINVAL for kind not 0/1, alpha not in [0,1], sigma < 0,
+ * n < 0, d/g out of range, ldx < d, NULL required pointers. */
+int esom_landmark_update(esom_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
+                         float *L_hd, const float *L_2d, int32_t g, int32_t kind, float alpha,
+                         float sigma, const int32_t *nearest, int32_t *counts, void *stream);
+
+/* Waits for the work enqueued on `stream`; ESOM_EDEVICE reports a device fault. */
+int esom_sync(esom_ctx *ctx, void *stream);
+
+/* Synchronises `stream`, then copies the context's counters into *stats
+ * (host pointer); if reset != 0 the counters restart from zero. */
+int esom_get_stats(esom_ctx *ctx, void *stream, esom_stats *stats, int32_t reset);
+
+/* enable != 0: every following esom_embed on this context records HIP events
+ * on its stream around the landmark preparation, the fused kernel and the
+ * exact path; esom_get_stats adds their elapsed times to ms_prep / ms_main /
+ * ms_exact.  Timing serialises nothing but costs six event records per call. */
+int esom_set_timing(esom_ctx *ctx, int32_t enable);
+
+#ifdef __cplusplus
+}
+#endif
+
+#endif /* ESOM_H */

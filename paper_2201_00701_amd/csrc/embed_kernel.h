@@ -1,0 +1,465 @@
+// Fused EmbedSOM kernel for gfx950 (one wavefront = 64 points).
+//
+// Phase A, screen (MFMA).  The wave holds its 64 points as two 32-point MFMA
+// B operands (centred on the landmark centroid, BF16 or FP32) in registers
+// and streams 32-landmark A tiles (-2 (L_j - c), prepared once per landmark
+// set).  v_mfma_f32_32x32x* with C initialised to |L_j - c|^2 gives
+//   key_ij = |L_j - c|^2 - 2 <x_i - c, L_j - c>  =  delta_ij^2 - |x_i - c|^2,
+// so keys rank the landmarks of a point exactly like the distances do.  In
+// the 32x32 output layout lane l holds 16 keys of point (l mod 32); the two
+// lanes l and l+32 of a point see disjoint halves of every tile.
+//   Pass 1 keeps, per lane, the minimum key of 32 landmark groups (register
+//   slot x tile parity).  A lane's j-th smallest group minimum bounds from
+//   above j distinct keys of its half, so with j = ceil(C/2) the larger of the
+//   two lanes' values, tau, has at least C keys at or below it.
+//   Pass 2 recomputes the keys and shifts one bit per key (key <= tau) into a
+//   per-lane bitmap in LDS: the candidate set, with no capacity limit.
+// Phase B, exact selection (one lane = one point).  Every candidate is
+// rescored with exact FP32 differences and inserted into a sorted register
+// list; keys are doubles packing (delta^2, landmark index) so a plain
+// min/max network orders them lexicographically.  A point is certified when
+// its k-th rescored distance lies below tau by more than a rigorous bound of
+// the screen's rounding error (every non-candidate then lies farther away).
+// Phase C, projection (FP32, FP64 solve).  Scores from the k distances; the
+// pair terms use D_uv = 1/2 + (delta_u^2 - delta_v^2) / (2 |L_u - L_v|^2)
+// (polarisation of the segment projection) with the pair table from the
+// landmark preparation; Cramer's rule in FP64.
+// Points the fast path cannot vouch for (uncertified screen, k-th/(k+1)-th
+// tie below FP32 resolution, ill-conditioned system, degenerate
+// neighbourhood) are appended to a list and recomputed by the exact FP64
+// kernel afterwards.
+#pragma once
+
+#include <float.h>
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "esom_internal.h"
+
+namespace esom {
+
+typedef float f32x16 __attribute__((ext_vector_type(16)));
+typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
+typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
+
+constexpr float U32 = 5.9604645e-08f;     // 2^-24, FP32 unit roundoff
+constexpr float UBF16 = 0.00390625f;      // 2^-8, BF16 unit roundoff
+constexpr float ILL_PAIR = 64.0f;         // max(delta^2)/(2|L_u-L_v|^2) beyond this: exact path
+constexpr double ILL_COND = 64.0;         // (tr/2)^2/det beyond this: exact path
+
+__device__ __forceinline__ unsigned bf16_bits_rne(float f) {
+    unsigned u = __float_as_uint(f);
+    u += 0x7FFFu + ((u >> 16) & 1u);
+    return u >> 16;
+}
+
+__device__ __forceinline__ double pack_key(float d2, int j) {
+    unsigned long long b = (unsigned long long)__double_as_longlong((double)d2);
+    return __longlong_as_double((long long)(b | (unsigned long long)j));
+}
+__device__ __forceinline__ float key_d2(double v) {
+    unsigned long long b = (unsigned long long)__double_as_longlong(v);
+    return (float)__longlong_as_double((long long)(b & ~0x1FFFull));
+}
+__device__ __forceinline__ int key_idx(double v) {
+    return (int)((unsigned long long)__double_as_longlong(v) & 0x1FFFull);
+}
+
+// Ascending bitonic sort of N floats held in registers (N a power of two).
+template <int N>
+__device__ __forceinline__ void sort_regs(float (&v)[N]) {
+#pragma unroll
+    for (int k = 2; k <= N; k <<= 1) {
+#pragma unroll
+        for (int j = k >> 1; j > 0; j >>= 1) {
+#pragma unroll
+            for (int i = 0; i < N; ++i) {
+                const int l = i ^ j;
+                if (l > i) {
+                    const float a = v[i], b = v[l];
+                    const bool up = (i & k) == 0;
+                    v[i] = up ? fminf(a, b) : fmaxf(a, b);
+                    v[l] = up ? fmaxf(a, b) : fminf(a, b);
+                }
+            }
+        }
+    }
+}
+
+template <int KP>
+__device__ __forceinline__ void insert_sorted(double (&s)[KP], double &rej, double v) {
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+        const double lo = fmin(s[q], v);
+        v = fmax(s[q], v);
+        s[q] = lo;
+    }
+    rej = fmin(rej, v);
+}
+
+// Bytes of LDS one wave needs.
+__host__ __device__ inline int wave_smem_bytes(int kp, int npair_tiles) {
+    const int bits = 2 * npair_tiles * 64 * 4;
+    const int nbr = kp * 64 * 10;
+    return (bits > nbr ? bits : nbr) + 512;
+}
+
+template <int MODE, int DC>
+struct PointOperand;
+
+template <int DC>
+struct PointOperand<1, DC> {  // BF16: lane holds dims 16c + 8h + e of its point
+    bf16x8 b[2][DC];
+};
+template <int DC>
+struct PointOperand<0, DC> {  // FP32: lane holds dims 2s + h, s < 8 DC
+    float b[2][8 * DC];
+};
+
+template <int MODE, int DC>
+__device__ __forceinline__ void screen_tile(const EmbedArgs &a, const PointOperand<MODE, DC> &P,
+                                            int t, int lane, f32x16 (&acc)[2]) {
+    const int h = lane >> 5;
+    f32x16 nrm;
+    {
+        const float4 *np = reinterpret_cast<const float4 *>(a.norms + (size_t)(t * 2 + h) * 16);
+        float4 n0 = np[0], n1 = np[1], n2 = np[2], n3 = np[3];
+        nrm[0] = n0.x; nrm[1] = n0.y; nrm[2] = n0.z; nrm[3] = n0.w;
+        nrm[4] = n1.x; nrm[5] = n1.y; nrm[6] = n1.z; nrm[7] = n1.w;
+        nrm[8] = n2.x; nrm[9] = n2.y; nrm[10] = n2.z; nrm[11] = n2.w;
+        nrm[12] = n3.x; nrm[13] = n3.y; nrm[14] = n3.z; nrm[15] = n3.w;
+    }
+    acc[0] = nrm;
+    acc[1] = nrm;
+    if constexpr (MODE == 1) {
+        const u32x4 *Ap = reinterpret_cast<const u32x4 *>(a.A) + (size_t)t * DC * 64 + lane;
+#pragma unroll
+        for (int c = 0; c < DC; ++c) {
+            const bf16x8 av = __builtin_bit_cast(bf16x8, Ap[c * 64]);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, P.b[0][c], acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, P.b[1][c], acc[1], 0, 0, 0);
+        }
+    } else {
+        const float *Ap = reinterpret_cast<const float *>(a.A) + (size_t)t * (8 * DC) * 64 + lane;
+#pragma unroll
+        for (int s = 0; s < 8 * DC; ++s) {
+            const float av = Ap[s * 64];
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, P.b[0][s], acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, P.b[1][s], acc[1], 0, 0, 0);
+        }
+    }
+}
+
+template <int MODE, int DC, int KP>
+__global__ void __launch_bounds__(256) embed_main(EmbedArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    constexpr int DP = 16 * DC;
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    const int h = lane >> 5;
+    const int i32 = lane & 31;
+    const int W = a.npair_tiles;
+    unsigned char *wsm = smem + (size_t)wave * wave_smem_bytes(KP, W);
+    unsigned *bitsL = reinterpret_cast<unsigned *>(wsm);
+    float *nbD2 = reinterpret_cast<float *>(wsm);
+    float *nbS = nbD2 + KP * 64;
+    unsigned short *nbI = reinterpret_cast<unsigned short *>(nbS + KP * 64);
+    const int tail = (2 * W * 64 * 4 > KP * 64 * 10) ? 2 * W * 64 * 4 : KP * 64 * 10;
+    float *tauL = reinterpret_cast<float *>(wsm + tail);
+    float *xnL = tauL + 64;
+
+    const float lmax = *a.lmax;
+    const float us = (MODE == 1) ? UBF16 : U32;
+
+    unsigned long long st_cand = 0;
+    const int64_t nwt = (a.n + 63) / 64;
+    for (int64_t wt = (int64_t)blockIdx.x * wpb + wave; wt < nwt; wt += (int64_t)gridDim.x * wpb) {
+        const int64_t pbase = wt * 64;
+
+        // ---------------- point operands (centred), and |x - c|^2
+        PointOperand<MODE, DC> P;
+        float xnp[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const int64_t pi = pbase + 32 * p + i32;
+            const bool valid = pi < a.n;
+            const float *xr = a.X + (valid ? pi : 0) * a.ldx;
+            float part = 0.f;
+            if constexpr (MODE == 1) {
+#pragma unroll
+                for (int c = 0; c < DC; ++c) {
+                    unsigned w[4];
+#pragma unroll
+                    for (int e = 0; e < 8; e += 2) {
+                        const int d0 = 16 * c + 8 * h + e;
+                        const float v0 = (valid && d0 < a.d) ? xr[d0] - a.cent[d0] : 0.f;
+                        const float v1 = (valid && d0 + 1 < a.d) ? xr[d0 + 1] - a.cent[d0 + 1] : 0.f;
+                        part = fmaf(v0, v0, part);
+                        part = fmaf(v1, v1, part);
+                        w[e >> 1] = bf16_bits_rne(v0) | (bf16_bits_rne(v1) << 16);
+                    }
+                    u32x4 wv = {w[0], w[1], w[2], w[3]};
+                    P.b[p][c] = __builtin_bit_cast(bf16x8, wv);
+                }
+            } else {
+#pragma unroll
+                for (int s = 0; s < 8 * DC; ++s) {
+                    const int dd = 2 * s + h;
+                    const float v = (valid && dd < a.d) ? xr[dd] - a.cent[dd] : 0.f;
+                    part = fmaf(v, v, part);
+                    P.b[p][s] = v;
+                }
+            }
+            xnp[p] = part + __shfl_xor(part, 32);
+        }
+
+        // ---------------- pass 1: group minima of the keys
+        float gmin[2][2][16];
+#pragma unroll
+        for (int p = 0; p < 2; ++p)
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) gmin[p][q][r] = INFINITY;
+        for (int tp = 0; tp < W; ++tp) {
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                f32x16 acc[2];
+                screen_tile<MODE, DC>(a, P, 2 * tp + half, lane, acc);
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r) gmin[p][half][r] = fminf(gmin[p][half][r], acc[p][r]);
+            }
+        }
+        // threshold: a lane's jsel-th smallest group minimum, max over the pair of lanes
+        float tau[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            float v[32];
+#pragma unroll
+            for (int q = 0; q < 2; ++q)
+#pragma unroll
+                for (int r = 0; r < 16; ++r) v[16 * q + r] = gmin[p][q][r];
+            sort_regs<32>(v);
+            float tl = v[31];
+#pragma unroll
+            for (int q = 0; q < 32; ++q)
+                if (q == a.jsel - 1) tl = v[q];
+            const float tt = fmaxf(tl, __shfl_xor(tl, 32));
+            tau[p] = fminf(tt, FLT_MAX);
+        }
+
+        // ---------------- pass 2: candidate bitmaps (key <= tau) into LDS
+        for (int tp = 0; tp < W; ++tp) {
+            unsigned cur[2] = {0u, 0u};
+#pragma unroll
+            for (int half = 0; half < 2; ++half) {
+                f32x16 acc[2];
+                screen_tile<MODE, DC>(a, P, 2 * tp + half, lane, acc);
+#pragma unroll
+                for (int p = 0; p < 2; ++p)
+#pragma unroll
+                    for (int r = 0; r < 16; ++r)
+                        cur[p] = (cur[p] << 1) | (acc[p][r] <= tau[p] ? 1u : 0u);
+            }
+#pragma unroll
+            for (int p = 0; p < 2; ++p) bitsL[(p * W + tp) * 64 + lane] = cur[p];
+        }
+        if (h == 0) {
+            tauL[i32] = tau[0];
+            tauL[32 + i32] = tau[1];
+            xnL[i32] = xnp[0];
+            xnL[32 + i32] = xnp[1];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+        // ---------------- phase B: one lane per point (lane l <-> point pbase + l)
+        const int64_t pi = pbase + lane;
+        const bool valid = pi < a.n;
+        const float tau_p = tauL[lane];
+        const float xn = xnL[lane];
+        float x[DP];
+        {
+            const float *xr = a.X + (valid ? pi : 0) * a.ldx;
+#pragma unroll
+            for (int t = 0; t < DP; ++t) x[t] = (valid && t < a.d) ? xr[t] : 0.f;
+        }
+        double sk[KP];
+#pragma unroll
+        for (int q = 0; q < KP; ++q) sk[q] = INFINITY;
+        double rej = INFINITY;
+        int m = 0;
+        for (int tp = 0; tp < W; ++tp) {
+#pragma unroll
+            for (int hh = 0; hh < 2; ++hh) {
+                unsigned b = bitsL[(h * W + tp) * 64 + i32 + 32 * hh];
+                if (!valid) b = 0u;
+                while (b) {
+                    const int pos = __clz((int)b);
+                    b &= ~(0x80000000u >> pos);
+                    const int t = 2 * tp + (pos >> 4);
+                    const int r = pos & 15;
+                    const int j = 32 * t + 8 * (r >> 2) + 4 * hh + (r & 3);
+                    const float4 *Lr = reinterpret_cast<const float4 *>(a.Lpad + (size_t)j * DP);
+                    float acc = 0.f;
+#pragma unroll
+                    for (int q = 0; q < DP / 4; ++q) {
+                        const float4 lv = Lr[q];
+                        const float e0 = x[4 * q] - lv.x, e1 = x[4 * q + 1] - lv.y;
+                        const float e2 = x[4 * q + 2] - lv.z, e3 = x[4 * q + 3] - lv.w;
+                        acc = fmaf(e0, e0, acc);
+                        acc = fmaf(e1, e1, acc);
+                        acc = fmaf(e2, e2, acc);
+                        acc = fmaf(e3, e3, acc);
+                    }
+                    insert_sorted<KP>(sk, rej, pack_key(acc, j));
+                    ++m;
+                }
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+
+        // k-th and (k+1)-th rescored distances
+        float d2k = 0.f, d2k1 = INFINITY, d2first = key_d2(sk[0]);
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            if (q == a.k - 1) d2k = key_d2(sk[q]);
+            if (q == a.k) d2k1 = key_d2(sk[q]);
+        }
+        if (a.k >= KP) d2k1 = (rej < INFINITY) ? key_d2(rej) : INFINITY;
+
+        unsigned reason = 0;
+        {
+            const float sx = sqrtf(xn);
+            const float E = 1.01f * (2.f * (2.f * us + us * us) * sx * lmax +
+                                     (2.f * DP + 16.f) * U32 * (sx + lmax) * (sx + lmax));
+            float rhs = tau_p + xn - E;
+            rhs -= 4.f * U32 * (fabsf(tau_p) + xn + E);
+            const bool cert = (tau_p >= FLT_MAX) || (d2k * (1.f + (DP + 3) * U32) < rhs);
+            if (!cert || m < a.k) reason |= R_UNCERT;
+            if (m > a.k && d2k1 - d2k <= 4.f * (DP + 3) * U32 * d2k1) reason |= R_NEARTIE;
+        }
+
+        // knn outputs (overwritten by the exact path for listed points)
+        if (valid && (a.knn_idx || a.knn_d2)) {
+#pragma unroll
+            for (int q = 0; q < KP; ++q) {
+                if (q < a.k) {
+                    if (a.knn_idx) a.knn_idx[pi * a.k + q] = key_idx(sk[q]);
+                    if (a.knn_d2) a.knn_d2[pi * a.k + q] = key_d2(sk[q]);
+                }
+            }
+        }
+
+        if (!a.knn_only) {
+            // ---------------- phase C: scores
+            float dl[KP];
+            float mu = 0.f;
+#pragma unroll
+            for (int q = 0; q < KP; ++q) {
+                dl[q] = (q < a.k) ? sqrtf(key_d2(sk[q])) : 0.f;
+                if (q < a.k) mu = fmaf(dl[q], 1.f / (float)(q + 1), mu);
+            }
+            mu /= a.Wk;
+            float var = 0.f;
+#pragma unroll
+            for (int q = 0; q < KP; ++q) {
+                if (q < a.k) {
+                    const float e = dl[q] - mu;
+                    var = fmaf(e * e, 1.f / (float)(q + 1), var);
+                }
+            }
+            var /= a.Wk;
+            const float dk = sqrtf(d2k);
+            const bool flat = !(var > 1e-30f * mu * mu);
+            const float isig = flat ? 0.f : a.boost * rsqrtf(var);
+            if (d2first == d2k) reason |= R_DEGEN;
+            const int lu0 = key_idx(sk[0]);
+            const float ox = a.l2d[2 * lu0], oy = a.l2d[2 * lu0 + 1];
+            float ssum = 0.f;
+            float M00 = 0.f, M01 = 0.f, M11 = 0.f, r0 = 0.f, r1 = 0.f;
+#pragma unroll
+            for (int q = 0; q < KP; ++q) {
+                if (q < a.k) {
+                    const float e = flat ? 1.f : __expf((mu - dl[q]) * isig);
+                    const float c = a.use_cutoff ? -expm1f(a.cutoff * (dl[q] - dk) / dk) : 1.f;
+                    const float s = (d2first == d2k) ? 0.f : e * c;
+                    const int j = key_idx(sk[q]);
+                    const float lx = a.l2d[2 * j] - ox, ly = a.l2d[2 * j + 1] - oy;
+                    ssum += s;
+                    const float gs = a.gravity * s;
+                    M00 += gs;
+                    M11 += gs;
+                    r0 = fmaf(gs, lx, r0);
+                    r1 = fmaf(gs, ly, r1);
+                    nbD2[q * 64 + lane] = key_d2(sk[q]);
+                    nbS[q * 64 + lane] = s;
+                    nbI[q * 64 + lane] = (unsigned short)j;
+                }
+            }
+            if (!(ssum > 0.f)) reason |= R_DEGEN;
+            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+            __builtin_amdgcn_wave_barrier();
+            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+
+            // ---------------- pairs (i < j among the neighbours with non-zero score)
+            const bool unit_adjust = a.adjust == 1.0f;
+            bool ill = false;
+            for (int qi = 0; qi < a.kact; ++qi) {
+                const float d2i = nbD2[qi * 64 + lane], si = nbS[qi * 64 + lane];
+                const int ui = nbI[qi * 64 + lane];
+                const float lxi = a.l2d[2 * ui] - ox, lyi = a.l2d[2 * ui + 1] - oy;
+                const float *invrow = a.inv2 + (size_t)ui * a.g;
+                for (int qj = qi + 1; qj < a.kact; ++qj) {
+                    const float d2j = nbD2[qj * 64 + lane], sj = nbS[qj * 64 + lane];
+                    const int vj = nbI[qj * 64 + lane];
+                    const float2 lv = reinterpret_cast<const float2 *>(a.l2d)[vj];
+                    const float hx = (lv.x - ox) - lxi, hy = (lv.y - oy) - lyi;
+                    const float inv = invrow[vj];
+                    const float hh = fmaf(hx, hx, hy * hy);
+                    if (inv < 0.f || hh == 0.f) continue;
+                    if (fmaxf(d2i, d2j) * inv > ILL_PAIR) ill = true;
+                    const float D = fmaf(d2i - d2j, inv, 0.5f);
+                    const float ihh = 1.f / hh;
+                    const float q = si * sj * (unit_adjust ? ihh : exp2f(-a.adjust * __log2f(hh)));
+                    const float qh = q * ihh;
+                    const float t = fmaf(D, hh, fmaf(hx, lxi, hy * lyi));
+                    const float qhx = qh * hx, qhy = qh * hy;
+                    M00 = fmaf(qhx, hx, M00);
+                    M01 = fmaf(qhx, hy, M01);
+                    M11 = fmaf(qhy, hy, M11);
+                    r0 = fmaf(qhx, t, r0);
+                    r1 = fmaf(qhy, t, r1);
+                }
+            }
+            // ---------------- 2x2 solve in FP64 (Cramer's rule)
+            const double m00 = M00, m01 = M01, m11 = M11, rr0 = r0, rr1 = r1;
+            const double det = m00 * m11 - m01 * m01;
+            const double tr = m00 + m11;
+            if (ill || !(det > 0.0) || 0.25 * tr * tr > ILL_COND * det) reason |= R_ILLCOND;
+            if (valid && reason == 0) {
+                const double px = (rr0 * m11 - m01 * rr1) / det;
+                const double py = (m00 * rr1 - m01 * rr0) / det;
+                a.out[2 * pi] = (float)((double)ox + px);
+                a.out[2 * pi + 1] = (float)((double)oy + py);
+            }
+            __builtin_amdgcn_wave_barrier();
+        }
+        if (valid && reason) {
+            const unsigned long long slot = atomicAdd(&a.counters[C_FB_LEN], 1ull);
+            a.fb_list[slot] = (int32_t)pi;
+            a.fb_reason[slot] = (uint8_t)reason;
+        }
+        st_cand += valid ? (unsigned long long)m : 0ull;
+    }
+    // wave-level totals
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) st_cand += __shfl_xor(st_cand, o);
+    if (lane == 0 && st_cand) atomicAdd(&a.counters[C_CAND], st_cand);
+}
+
+}  // namespace esom

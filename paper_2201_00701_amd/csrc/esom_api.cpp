@@ -1,0 +1,478 @@
+// C ABI of libesom: argument validation, context and scratch management, and
+// the launch sequence of each entry point (see include/esom.h).
+#include <hip/hip_runtime.h>
+#include <math.h>
+#include <stdarg.h>
+#include <stdio.h>
+#include <string.h>
+
+#include <string>
+#include <vector>
+
+#include "esom_internal.h"
+
+using namespace esom;
+
+struct esom_ctx {
+    int device = 0;
+    int num_cus = 0;
+    size_t budget = 0;  // 0 = unbounded
+    size_t held = 0;    // bytes currently allocated
+    unsigned long long *counters = nullptr;
+    // embed scratch arena
+    void *arena = nullptr;
+    size_t arena_bytes = 0;
+    int64_t cap_n = 0;
+    int cap_g = 0, cap_dp = 0;
+    Scratch sc;
+    // landmark-update workspace
+    void *uws = nullptr;
+    size_t uws_bytes = 0;
+    int32_t *nearest = nullptr;
+    int64_t nearest_cap = 0;
+    // optional per-kernel timing: pending event quadruples (prep, main, exact, end)
+    bool timing = false;
+    std::vector<hipEvent_t> pending;
+    int64_t n_timed = 0;
+    double ms_prep = 0.0, ms_main = 0.0, ms_exact = 0.0;
+};
+
+namespace {
+
+thread_local std::string t_err;
+
+int fail(int code, const char *fmt, ...) {
+    char buf[512];
+    va_list ap;
+    va_start(ap, fmt);
+    vsnprintf(buf, sizeof buf, fmt, ap);
+    va_end(ap);
+    t_err = buf;
+    return code;
+}
+
+int hip_fail(hipError_t e, const char *what) {
+    return fail(ESOM_EDEVICE, "%s: %s", what, hipGetErrorString(e));
+}
+
+size_t align256(size_t b) { return (b + 255) & ~(size_t)255; }
+
+bool aligned4(const void *p) { return ((uintptr_t)p & 3u) == 0; }
+
+int dev_alloc(esom_ctx *c, void **p, size_t bytes) {
+    if (c->budget && c->held + bytes > c->budget)
+        return fail(ESOM_ENOMEM, "scratch of %zu bytes exceeds the context budget (%zu held of %zu)",
+                    bytes, c->held, c->budget);
+    hipError_t e = hipMalloc(p, bytes);
+    if (e != hipSuccess) return fail(ESOM_ENOMEM, "hipMalloc(%zu): %s", bytes, hipGetErrorString(e));
+    c->held += bytes;
+    return ESOM_OK;
+}
+
+void dev_free(esom_ctx *c, void *&p, size_t bytes) {
+    if (p) {
+        (void)hipFree(p);
+        c->held -= bytes;
+        p = nullptr;
+    }
+}
+
+// Lays the embed scratch out for (n, g, dp) capacities.
+size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp) {
+    const int ntiles = ((g + TILE_PAIR - 1) / TILE_PAIR) * 2;
+    char *p = static_cast<char *>(base);
+    size_t off = 0;
+    auto take = [&](size_t bytes) {
+        void *r = base ? p + off : nullptr;
+        off += align256(bytes);
+        return r;
+    };
+    sc.prep.cent = static_cast<float *>(take(sizeof(float) * dp));
+    sc.prep.A = take(sizeof(float) * (size_t)ntiles * TILE * dp);
+    sc.prep.norms = static_cast<float *>(take(sizeof(float) * (size_t)ntiles * TILE));
+    sc.prep.Lpad = static_cast<float *>(take(sizeof(float) * (size_t)g * dp));
+    sc.prep.inv2 = static_cast<float *>(take(sizeof(float) * (size_t)g * g));
+    sc.prep.lmax = static_cast<float *>(take(sizeof(float)));
+    sc.fb_list = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
+    sc.fb_reason = static_cast<uint8_t *>(take((size_t)(n > 0 ? n : 1)));
+    return off;
+}
+
+int ensure_scratch(esom_ctx *c, int64_t n, int g, int dp, hipStream_t s) {
+    if (c->arena && n <= c->cap_n && g <= c->cap_g && dp <= c->cap_dp) return ESOM_OK;
+    int64_t nn = n > c->cap_n ? n + n / 4 : c->cap_n;
+    int gg = g > c->cap_g ? g : c->cap_g;
+    int dd = dp > c->cap_dp ? dp : c->cap_dp;
+    const size_t bytes = carve(c->sc, nullptr, nn, gg, dd);
+    if (c->arena) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+        dev_free(c, c->arena, c->arena_bytes);
+        c->arena_bytes = 0;
+    }
+    int st = dev_alloc(c, &c->arena, bytes);
+    if (st != ESOM_OK) {
+        c->cap_n = c->cap_g = c->cap_dp = 0;
+        return st;
+    }
+    c->arena_bytes = bytes;
+    carve(c->sc, c->arena, nn, gg, dd);
+    c->cap_n = nn;
+    c->cap_g = gg;
+    c->cap_dp = dd;
+    return ESOM_OK;
+}
+
+double harmonic(int k) {
+    double h = 0.0;
+    for (int i = 1; i <= k; ++i) h += 1.0 / i;
+    return h;
+}
+
+int validate_common(const float *X, int64_t n, int32_t d, int64_t ldx, const float *L, int32_t g) {
+    if (n < 0) return fail(ESOM_EINVAL, "n = %lld < 0", (long long)n);
+    if (d < 1 || d > ESOM_MAX_D) return fail(ESOM_EINVAL, "d = %d outside [1, %d]", d, ESOM_MAX_D);
+    if (g < 1 || g > ESOM_MAX_G) return fail(ESOM_EINVAL, "g = %d outside [1, %d]", g, ESOM_MAX_G);
+    if (ldx < d) return fail(ESOM_EINVAL, "ldx = %lld < d = %d", (long long)ldx, d);
+    if (!L || !aligned4(L)) return fail(ESOM_EINVAL, "L_hd is NULL or not 4-byte aligned");
+    if (n > 0 && (!X || !aligned4(X))) return fail(ESOM_EINVAL, "X is NULL or not 4-byte aligned");
+    if (n > (int64_t)INT32_MAX) return fail(ESOM_EINVAL, "n = %lld exceeds 2^31 - 1", (long long)n);
+    return ESOM_OK;
+}
+
+struct Plan {
+    int dp, dc, kp, C, jsel;
+    bool fast;
+};
+
+Plan make_plan(int d, int g, int k, int mode, int candidates) {
+    Plan p;
+    p.dp = 16 * ((d + 15) / 16);
+    p.dc = p.dp / 16;
+    p.kp = k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 0;
+    const int maxdc = mode == 1 ? FAST_MAX_DC_BF16 : FAST_MAX_DC_FP32;
+    p.fast = p.kp != 0 && p.dc <= maxdc && g <= FAST_MAX_G;
+    int C = candidates > 0 ? candidates : (mode == 1 ? 2 * k : k + 2);
+    if (C < k + 1) C = k + 1;
+    p.C = C;
+    p.jsel = (C + 1) / 2;
+    if (p.jsel > 32) p.jsel = 32;
+    if (p.jsel < 1) p.jsel = 1;
+    return p;
+}
+
+// Enqueues preparation + fast kernel + exact path.  knn_only: k-nearest only.
+int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const float *L,
+              const float *l2d, int g, const esom_params &P, float *out, int32_t *knn_idx,
+              float *knn_d2, int knn_only, hipStream_t s) {
+    const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
+    int st = ensure_scratch(c, n, g, pl.dp, s);
+    if (st != ESOM_OK) return st;
+    Prep &pr = c->sc.prep;
+    pr.g = g;
+    pr.d = d;
+    pr.dp = pl.dp;
+    pr.dc = pl.dc;
+    pr.ntiles = ((g + TILE_PAIR - 1) / TILE_PAIR) * 2;
+    pr.npairs = pr.ntiles / 2;
+    pr.mode = P.mode;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    const bool timed = c->timing && !knn_only;
+    if (timed) {
+        for (int i = 0; i < 4; ++i) {
+            hipError_t ee = hipEventCreate(&ev[i]);
+            if (ee != hipSuccess) return hip_fail(ee, "hipEventCreate");
+        }
+        (void)hipEventRecord(ev[0], s);
+    }
+    hipError_t e = launch_prep(pr, L, P.mode, c->counters, knn_only ? 0 : (long long)n, s);
+    if (e != hipSuccess) return hip_fail(e, "landmark preparation launch");
+    if (timed) (void)hipEventRecord(ev[1], s);
+
+    EmbedArgs a;
+    memset(&a, 0, sizeof a);
+    a.X = X;
+    a.n = n;
+    a.ldx = ldx;
+    a.d = d;
+    a.dp = pl.dp;
+    a.g = g;
+    a.ntiles = pr.ntiles;
+    a.npair_tiles = pr.npairs;
+    a.A = pr.A;
+    a.norms = pr.norms;
+    a.cent = pr.cent;
+    a.Lpad = pr.Lpad;
+    a.l2d = l2d;
+    a.inv2 = pr.inv2;
+    a.lmax = pr.lmax;
+    a.k = P.k;
+    a.kact = P.k < g ? P.k - 1 : P.k;
+    a.jsel = pl.jsel;
+    a.use_cutoff = P.k < g ? 1 : 0;
+    a.boost = P.boost;
+    a.cutoff = P.cutoff;
+    a.gravity = P.gravity;
+    a.adjust = P.adjust;
+    a.Wk = (float)harmonic(P.k);
+    a.out = out;
+    a.knn_idx = knn_idx;
+    a.knn_d2 = knn_d2;
+    a.fb_list = c->sc.fb_list;
+    a.fb_reason = c->sc.fb_reason;
+    a.counters = c->counters;
+    a.knn_only = knn_only;
+    if (pl.fast) {
+        e = launch_embed(a, P.mode, pl.kp, c->num_cus, s);
+        if (e != hipSuccess) return hip_fail(e, "embed kernel launch");
+        if (timed) (void)hipEventRecord(ev[2], s);
+        e = launch_fallback(a, c->num_cus, s);
+        if (e != hipSuccess) return hip_fail(e, "exact-path launch");
+    } else {
+        if (timed) (void)hipEventRecord(ev[2], s);
+        e = launch_all_to_fallback(a, c->num_cus, s);
+        if (e != hipSuccess) return hip_fail(e, "exact-path launch");
+    }
+    if (timed) {
+        (void)hipEventRecord(ev[3], s);
+        for (int i = 0; i < 4; ++i) c->pending.push_back(ev[i]);
+    }
+    return ESOM_OK;
+}
+
+}  // namespace
+
+extern "C" {
+
+void esom_default_params(esom_params *p) {
+    if (!p) return;
+    p->k = 16;
+    p->boost = 1.0f;
+    p->adjust = 1.0f;
+    p->cutoff = 10.0f;
+    p->gravity = 1e-5f;
+    p->mode = ESOM_MODE_FP32;
+    p->candidates = 0;
+}
+
+const char *esom_last_error(void) { return t_err.c_str(); }
+
+int esom_create(int device, size_t hbm_budget_bytes, esom_ctx **out) {
+    t_err.clear();
+    if (!out) return fail(ESOM_EINVAL, "out is NULL");
+    *out = nullptr;
+    int ndev = 0;
+    hipError_t e = hipGetDeviceCount(&ndev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDeviceCount");
+    if (device < 0 || device >= ndev)
+        return fail(ESOM_EINVAL, "device %d outside [0, %d)", device, ndev);
+    e = hipSetDevice(device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    esom_ctx *c = new esom_ctx();
+    c->device = device;
+    c->budget = hbm_budget_bytes;
+    hipDeviceProp_t prop;
+    e = hipGetDeviceProperties(&prop, device);
+    if (e != hipSuccess) {
+        delete c;
+        return hip_fail(e, "hipGetDeviceProperties");
+    }
+    c->num_cus = prop.multiProcessorCount;
+    int st = dev_alloc(c, reinterpret_cast<void **>(&c->counters),
+                       sizeof(unsigned long long) * C_COUNT);
+    if (st != ESOM_OK) {
+        delete c;
+        return st;
+    }
+    e = hipMemset(c->counters, 0, sizeof(unsigned long long) * C_COUNT);
+    if (e != hipSuccess) {
+        dev_free(c, reinterpret_cast<void *&>(c->counters), sizeof(unsigned long long) * C_COUNT);
+        delete c;
+        return hip_fail(e, "hipMemset");
+    }
+    *out = c;
+    return ESOM_OK;
+}
+
+int esom_set_timing(esom_ctx *c, int32_t enable) {
+    t_err.clear();
+    if (!c) return fail(ESOM_EINVAL, "ctx is NULL");
+    c->timing = enable != 0;
+    return ESOM_OK;
+}
+
+void esom_destroy(esom_ctx *c) {
+    if (!c) return;
+    (void)hipSetDevice(c->device);
+    (void)hipDeviceSynchronize();
+    for (hipEvent_t ev : c->pending) (void)hipEventDestroy(ev);
+    c->pending.clear();
+    dev_free(c, c->arena, c->arena_bytes);
+    dev_free(c, c->uws, c->uws_bytes);
+    dev_free(c, reinterpret_cast<void *&>(c->nearest), sizeof(int32_t) * (size_t)c->nearest_cap);
+    dev_free(c, reinterpret_cast<void *&>(c->counters), sizeof(unsigned long long) * C_COUNT);
+    delete c;
+}
+
+int esom_embed(esom_ctx *c, const float *X, int64_t n, int32_t d, int64_t ldx, const float *L_hd,
+               const float *L_2d, int32_t g, const esom_params *params, float *out,
+               int32_t *knn_idx, float *knn_dist2, void *stream) {
+    t_err.clear();
+    if (!c) return fail(ESOM_EINVAL, "ctx is NULL");
+    if (!params) return fail(ESOM_EINVAL, "params is NULL");
+    int st = validate_common(X, n, d, ldx, L_hd, g);
+    if (st != ESOM_OK) return st;
+    const esom_params &P = *params;
+    if (g < 3) return fail(ESOM_EINVAL, "g = %d < 3", g);
+    if (P.k < 3 || P.k > g || P.k > ESOM_MAX_K)
+        return fail(ESOM_EINVAL, "k = %d outside [3, min(g = %d, %d)]", P.k, g, ESOM_MAX_K);
+    if (!(P.boost > 0.f) || !(P.boost * sqrt(harmonic(P.k)) < 80.0))
+        return fail(ESOM_EINVAL, "boost = %g must be > 0 with boost*sqrt(H_k) < 80", (double)P.boost);
+    if (!(P.cutoff > 0.f) || !isfinite(P.cutoff))
+        return fail(ESOM_EINVAL, "cutoff = %g must be finite and > 0", (double)P.cutoff);
+    if (!(P.gravity >= 0.f) || !isfinite(P.gravity))
+        return fail(ESOM_EINVAL, "gravity = %g must be finite and >= 0", (double)P.gravity);
+    if (!isfinite(P.adjust)) return fail(ESOM_EINVAL, "adjust must be finite");
+    if (P.mode != ESOM_MODE_FP32 && P.mode != ESOM_MODE_BF16_RESCORE)
+        return fail(ESOM_EINVAL, "unknown mode %d", P.mode);
+    if (P.candidates < 0 || P.candidates > g)
+        return fail(ESOM_EINVAL, "candidates = %d outside [0, g]", P.candidates);
+    if (!L_2d || !aligned4(L_2d)) return fail(ESOM_EINVAL, "L_2d is NULL or not 4-byte aligned");
+    if (n > 0 && (!out || ((uintptr_t)out & 7u)))
+        return fail(ESOM_EINVAL, "out is NULL or not 8-byte aligned");
+    if ((knn_idx && !aligned4(knn_idx)) || (knn_dist2 && !aligned4(knn_dist2)))
+        return fail(ESOM_EINVAL, "knn outputs must be 4-byte aligned");
+    if (((uintptr_t)L_2d & 7u)) return fail(ESOM_EINVAL, "L_2d must be 8-byte aligned");
+    if (n == 0) return ESOM_OK;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    return run_embed(c, X, n, d, ldx, L_hd, L_2d, g, P, out, knn_idx, knn_dist2, 0,
+                     static_cast<hipStream_t>(stream));
+}
+
+int esom_landmark_update(esom_ctx *c, const float *X, int64_t n, int32_t d, int64_t ldx,
+                         float *L_hd, const float *L_2d, int32_t g, int32_t kind, float alpha,
+                         float sigma, const int32_t *nearest, int32_t *counts, void *stream) {
+    t_err.clear();
+    if (!c) return fail(ESOM_EINVAL, "ctx is NULL");
+    int st = validate_common(X, n, d, ldx, L_hd, g);
+    if (st != ESOM_OK) return st;
+    if (kind != 0 && kind != 1) return fail(ESOM_EINVAL, "kind = %d must be 0 or 1", kind);
+    if (!(alpha >= 0.f && alpha <= 1.f)) return fail(ESOM_EINVAL, "alpha = %g outside [0, 1]", (double)alpha);
+    if (!(sigma >= 0.f) || !isfinite(sigma)) return fail(ESOM_EINVAL, "sigma = %g must be >= 0", (double)sigma);
+    if (kind == 1 && (!L_2d || ((uintptr_t)L_2d & 3u)))
+        return fail(ESOM_EINVAL, "L_2d is required (4-byte aligned) for the SOM update");
+    if ((nearest && !aligned4(nearest)) || (counts && !aligned4(counts)))
+        return fail(ESOM_EINVAL, "nearest/counts must be 4-byte aligned");
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const int32_t *near = nearest;
+    if (!near && n > 0) {
+        if (n > c->nearest_cap) {
+            if (c->nearest) {
+                e = hipStreamSynchronize(s);
+                if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+                dev_free(c, reinterpret_cast<void *&>(c->nearest), sizeof(int32_t) * (size_t)c->nearest_cap);
+            }
+            st = dev_alloc(c, reinterpret_cast<void **>(&c->nearest), sizeof(int32_t) * (size_t)n);
+            if (st != ESOM_OK) {
+                c->nearest_cap = 0;
+                return st;
+            }
+            c->nearest_cap = n;
+        }
+        esom_params P;
+        esom_default_params(&P);
+        P.k = 1;
+        P.mode = ESOM_MODE_FP32;
+        st = run_embed(c, X, n, d, ldx, L_hd, L_2d, g, P, nullptr, c->nearest, nullptr, 1, s);
+        if (st != ESOM_OK) return st;
+        near = c->nearest;
+    }
+    const size_t need = update_workspace_bytes(n, g, d);
+    if (need > c->uws_bytes) {
+        if (c->uws) {
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            dev_free(c, c->uws, c->uws_bytes);
+            c->uws_bytes = 0;
+        }
+        st = dev_alloc(c, &c->uws, need);
+        if (st != ESOM_OK) return st;
+        c->uws_bytes = need;
+    }
+    UpdateArgs u;
+    u.X = X;
+    u.n = n;
+    u.ldx = ldx;
+    u.d = d;
+    u.g = g;
+    u.kind = kind;
+    u.alpha = alpha;
+    u.sigma = sigma;
+    u.L = L_hd;
+    u.l2d = L_2d;
+    u.nearest = near;
+    u.counts = counts;
+    e = launch_update(u, c->uws, c->num_cus, s);
+    if (e != hipSuccess) return hip_fail(e, "landmark update launch");
+    return ESOM_OK;
+}
+
+int esom_sync(esom_ctx *c, void *stream) {
+    t_err.clear();
+    if (!c) return fail(ESOM_EINVAL, "ctx is NULL");
+    hipError_t e = hipSetDevice(c->device);
+    if (e == hipSuccess) e = hipStreamSynchronize(static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+    return ESOM_OK;
+}
+
+int esom_get_stats(esom_ctx *c, void *stream, esom_stats *stats, int32_t reset) {
+    t_err.clear();
+    if (!c || !stats) return fail(ESOM_EINVAL, "ctx or stats is NULL");
+    int st = esom_sync(c, stream);
+    if (st != ESOM_OK) return st;
+    unsigned long long h[C_COUNT];
+    hipError_t e = hipMemcpy(h, c->counters, sizeof h, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    stats->n_points = (int64_t)h[C_POINTS];
+    stats->n_fallback = (int64_t)h[C_FALLBACK];
+    stats->n_uncertified = (int64_t)h[C_UNCERT];
+    stats->n_near_tie = (int64_t)h[C_NEARTIE];
+    stats->n_illcond = (int64_t)h[C_ILLCOND];
+    stats->n_degenerate = (int64_t)h[C_DEGEN];
+    stats->n_candidates = (int64_t)h[C_CAND];
+    stats->n_slowpath = (int64_t)h[C_SLOW];
+    for (size_t i = 0; i + 3 < c->pending.size(); i += 4) {
+        float t01 = 0.f, t12 = 0.f, t23 = 0.f;
+        (void)hipEventSynchronize(c->pending[i + 3]);
+        (void)hipEventElapsedTime(&t01, c->pending[i], c->pending[i + 1]);
+        (void)hipEventElapsedTime(&t12, c->pending[i + 1], c->pending[i + 2]);
+        (void)hipEventElapsedTime(&t23, c->pending[i + 2], c->pending[i + 3]);
+        c->ms_prep += t01;
+        c->ms_main += t12;
+        c->ms_exact += t23;
+        c->n_timed += 1;
+    }
+    for (hipEvent_t ev : c->pending) (void)hipEventDestroy(ev);
+    c->pending.clear();
+    stats->n_timed = c->n_timed;
+    stats->ms_prep = c->ms_prep;
+    stats->ms_main = c->ms_main;
+    stats->ms_exact = c->ms_exact;
+    if (reset) {
+        c->n_timed = 0;
+        c->ms_prep = c->ms_main = c->ms_exact = 0.0;
+        e = hipMemset(c->counters, 0, sizeof h);
+        if (e != hipSuccess) return hip_fail(e, "hipMemset");
+        e = hipDeviceSynchronize();
+        if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");
+    }
+    return ESOM_OK;
+}
+
+}  // extern "C"

@@ -1,0 +1,100 @@
+// Internal declarations shared by the library's translation units.
+#pragma once
+
+#include <hip/hip_runtime.h>
+#include <stdint.h>
+
+#include "../../include/esom.h"
+
+namespace esom {
+
+// Screen tiles: 32 landmarks x 32 points per MFMA (v_mfma_f32_32x32x*).
+constexpr int TILE = 32;
+// Landmark count is padded to a multiple of 64 so tiles come in pairs.
+constexpr int TILE_PAIR = 64;
+// Fast-path limits (larger shapes go through the exact FP64 path).
+constexpr int FAST_MAX_KP = 32;
+constexpr int FAST_MAX_DC_BF16 = 8;  // d <= 128
+constexpr int FAST_MAX_DC_FP32 = 4;  // d <= 64
+constexpr int FAST_MAX_G = 4096;
+
+// Counter slots (uint64) in the context's device counter array.
+enum Counter {
+    C_FB_LEN = 0,    // length of this call's fallback list (reset per call)
+    C_POINTS = 1,
+    C_FALLBACK = 2,
+    C_UNCERT = 3,
+    C_NEARTIE = 4,
+    C_ILLCOND = 5,
+    C_DEGEN = 6,
+    C_CAND = 7,
+    C_SLOW = 8,
+    C_COUNT = 16,
+};
+
+// Fallback reasons (bit flags; a point may carry several).
+enum Reason { R_UNCERT = 1, R_NEARTIE = 2, R_ILLCOND = 4, R_DEGEN = 8 };
+
+// Prepared landmark set (device buffers owned by a scratch set).
+struct Prep {
+    int g = 0, d = 0, dp = 0, dc = 0, ntiles = 0, npairs = 0;
+    int mode = 0;
+    float *cent = nullptr;   // dp      centroid of L (FP32 of an FP64 mean)
+    void *A = nullptr;       // MFMA landmark operand, -2 (L - c), tile layout
+    float *norms = nullptr;  // ntiles * 32: |L_j - c|^2 in MFMA row order
+    float *Lpad = nullptr;   // g * dp:  L rows padded with zeros to dp
+    float *inv2 = nullptr;   // g * g:   1 / (2 |L_u - L_v|^2), -1 if zero
+    float *lmax = nullptr;   // 1:       max_j |L_j - c|
+};
+
+// Scratch memory for one in-flight embed (grows on demand).
+struct Scratch {
+    size_t cap_bytes = 0;
+    void *base = nullptr;
+    int64_t cap_n = 0;
+    int32_t *fb_list = nullptr;     // fallback point list (cap_n)
+    uint8_t *fb_reason = nullptr;   // per listed point reason flags (cap_n)
+    unsigned long long *counters = nullptr;  // C_COUNT
+    Prep prep;
+};
+
+struct EmbedArgs {
+    const float *X;
+    int64_t n, ldx;
+    int d, dp, g, ntiles, npair_tiles;
+    const void *A;
+    const float *norms, *cent, *Lpad, *l2d, *inv2, *lmax;
+    int k, kact, jsel;  // kact: neighbours with non-zero score; jsel: per-lane order statistic
+    int use_cutoff;
+    float boost, cutoff, gravity, adjust, Wk;
+    float *out;
+    int32_t *knn_idx;
+    float *knn_d2;
+    int32_t *fb_list;
+    uint8_t *fb_reason;
+    unsigned long long *counters;
+    int knn_only;  // 1: only write knn outputs (no projection)
+};
+
+// Launchers (esom_embed.hip).
+hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long long *counters,
+                       long long n_points, hipStream_t s);
+hipError_t launch_embed(const EmbedArgs &a, int mode, int kp, int num_cus, hipStream_t s);
+hipError_t launch_fallback(const EmbedArgs &a, int num_cus, hipStream_t s);
+hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, hipStream_t s);
+
+// Landmark update (esom_update.hip).
+struct UpdateArgs {
+    const float *X;
+    int64_t n, ldx;
+    int d, g, kind;
+    float alpha, sigma;
+    float *L;
+    const float *l2d;
+    const int32_t *nearest;
+    int32_t *counts;
+};
+size_t update_workspace_bytes(int64_t n, int g, int d);
+hipError_t launch_update(const UpdateArgs &u, void *ws, int num_cus, hipStream_t s);
+
+}  // namespace esom

@@ -1,0 +1,245 @@
+"""ctypes binding of libesom (include/esom.h): argument marshalling only.
+
+The functions named ``esom_*`` mirror the C entry points one to one and take
+raw device pointers (ints) and sizes.  ``Context`` adds torch conveniences:
+it takes device tensors, passes their ``data_ptr()`` and the current HIP
+stream, and raises ``EsomError`` on any non-zero status.  Every computation
+runs in the library's kernels; if the library is missing, loading fails
+loudly instead of falling back to anything else.
+"""
+from __future__ import annotations
+
+import ctypes
+import os
+import re
+
+HERE = os.path.dirname(os.path.abspath(__file__))
+LIB_PATH = os.path.join(HERE, "libesom.so")
+HEADER = os.path.join(os.path.dirname(HERE), "include", "esom.h")
+
+ESOM_OK = 0
+ESOM_EINVAL = -1
+ESOM_ENOMEM = -2
+ESOM_EDEVICE = -3
+ESOM_EBUSY = -4
+ESOM_ETIMEOUT = -5
+ESOM_ENOTFOUND = -6
+ESOM_MODE_FP32 = 0
+ESOM_MODE_BF16_RESCORE = 1
+MODES = {"fp32": ESOM_MODE_FP32, "bf16": ESOM_MODE_BF16_RESCORE}
+
+
+class esom_params(ctypes.Structure):
+    _fields_ = [("k", ctypes.c_int32), ("boost", ctypes.c_float), ("adjust", ctypes.c_float),
+                ("cutoff", ctypes.c_float), ("gravity", ctypes.c_float), ("mode", ctypes.c_int32),
+                ("candidates", ctypes.c_int32)]
+
+
+class esom_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "n_points", "n_fallback", "n_uncertified", "n_near_tie", "n_illcond", "n_degenerate",
+        "n_candidates", "n_slowpath", "n_timed")] + [
+        (n, ctypes.c_double) for n in ("ms_prep", "ms_main", "ms_exact")]
+
+    def as_dict(self):
+        return {n: (float if t is ctypes.c_double else int)(getattr(self, n))
+                for n, t in self._fields_}
+
+
+class EsomError(RuntimeError):
+    def __init__(self, code, msg):
+        super().__init__("esom error %d: %s" % (code, msg))
+        self.code = code
+
+
+_lib = None
+_vp, _i32, _i64, _f32, _sz = (ctypes.c_void_p, ctypes.c_int32, ctypes.c_int64, ctypes.c_float,
+                              ctypes.c_size_t)
+
+
+def load(path: str = LIB_PATH):
+    """Loads libesom.so (raises if it has not been built)."""
+    global _lib
+    if _lib is not None:
+        return _lib
+    if not os.path.exists(path):
+        raise RuntimeError("libesom.so not found at %s: build it with "
+                           "`python -m paper_2201_00701_amd.build`" % path)
+    lib = ctypes.CDLL(path)
+    lib.esom_default_params.argtypes = [ctypes.POINTER(esom_params)]
+    lib.esom_default_params.restype = None
+    lib.esom_create.argtypes = [ctypes.c_int, _sz, ctypes.POINTER(_vp)]
+    lib.esom_create.restype = ctypes.c_int
+    lib.esom_destroy.argtypes = [_vp]
+    lib.esom_destroy.restype = None
+    lib.esom_last_error.argtypes = []
+    lib.esom_last_error.restype = ctypes.c_char_p
+    lib.esom_embed.argtypes = [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32,
+                               ctypes.POINTER(esom_params), _vp, _vp, _vp, _vp]
+    lib.esom_embed.restype = ctypes.c_int
+    lib.esom_landmark_update.argtypes = [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32, _f32,
+                                         _f32, _vp, _vp, _vp]
+    lib.esom_landmark_update.restype = ctypes.c_int
+    lib.esom_sync.argtypes = [_vp, _vp]
+    lib.esom_sync.restype = ctypes.c_int
+    lib.esom_get_stats.argtypes = [_vp, _vp, ctypes.POINTER(esom_stats), _i32]
+    lib.esom_get_stats.restype = ctypes.c_int
+    lib.esom_set_timing.argtypes = [_vp, _i32]
+    lib.esom_set_timing.restype = ctypes.c_int
+    _lib = lib
+    return lib
+
+
+def header_functions(header: str = HEADER):
+    """Names of the functions include/esom.h declares."""
+    txt = open(header).read()
+    txt = re.sub(r"/\*.*?\*/", "", txt, flags=re.S)
+    return sorted(set(re.findall(r"\b(esom_[a-z_0-9]+)\s*\(", txt)))
+
+
+def _check(rc):
+    if rc != ESOM_OK:
+        raise EsomError(rc, load().esom_last_error().decode())
+    return rc
+
+
+# ---- same-name wrappers (raw pointers) -------------------------------------------
+
+def esom_default_params(**over) -> esom_params:
+    p = esom_params()
+    load().esom_default_params(ctypes.byref(p))
+    for k, v in over.items():
+        setattr(p, k, MODES.get(v, v) if k == "mode" else v)
+    return p
+
+
+def esom_create(device: int = 0, hbm_budget_bytes: int = 0) -> int:
+    h = _vp()
+    _check(load().esom_create(device, hbm_budget_bytes, ctypes.byref(h)))
+    return h.value
+
+
+def esom_destroy(ctx: int) -> None:
+    load().esom_destroy(ctx)
+
+
+def esom_last_error() -> str:
+    return load().esom_last_error().decode()
+
+
+def esom_embed(ctx, X, n, d, ldx, L_hd, L_2d, g, params, out, knn_idx=0, knn_dist2=0,
+               stream=0) -> int:
+    return load().esom_embed(ctx, X, n, d, ldx, L_hd, L_2d, g, ctypes.byref(params), out,
+                             knn_idx or None, knn_dist2 or None, stream or None)
+
+
+def esom_landmark_update(ctx, X, n, d, ldx, L_hd, L_2d, g, kind, alpha, sigma, nearest=0,
+                         counts=0, stream=0) -> int:
+    return load().esom_landmark_update(ctx, X, n, d, ldx, L_hd, L_2d or None, g, kind, alpha,
+                                       sigma, nearest or None, counts or None, stream or None)
+
+
+def esom_sync(ctx, stream=0) -> int:
+    return load().esom_sync(ctx, stream or None)
+
+
+def esom_get_stats(ctx, stream=0, reset=False) -> dict:
+    st = esom_stats()
+    _check(load().esom_get_stats(ctx, stream or None, ctypes.byref(st), 1 if reset else 0))
+    return st.as_dict()
+
+
+def esom_set_timing(ctx, enable=True) -> int:
+    return load().esom_set_timing(ctx, 1 if enable else 0)
+
+
+# ---- torch convenience ------------------------------------------------------------
+
+def _dev_f32(t, name, cols=None):
+    import torch
+    if not isinstance(t, torch.Tensor) or not t.is_cuda or t.dtype != torch.float32:
+        raise TypeError("%s must be a float32 device tensor" % name)
+    if t.dim() != 2 or (cols is not None and t.shape[1] != cols) or t.stride(1) != 1:
+        raise ValueError("%s must be 2-D with unit column stride%s" %
+                         (name, "" if cols is None else " and %d columns" % cols))
+    return t
+
+
+class Context:
+    """Owns an esom context on one device; methods take torch device tensors."""
+
+    def __init__(self, device: int = 0, hbm_budget_bytes: int = 0):
+        self.device = device
+        self.handle = esom_create(device, hbm_budget_bytes)
+
+    def close(self):
+        if self.handle:
+            esom_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _stream(stream):
+        import torch
+        if stream is None:
+            return torch.cuda.current_stream().cuda_stream
+        return getattr(stream, "cuda_stream", stream)
+
+    def embed(self, X, L, l, k=16, mode="fp32", boost=1.0, adjust=1.0, cutoff=10.0,
+              gravity=1e-5, candidates=0, out=None, knn=False, stream=None):
+        """Returns out (n x 2), or (out, knn_idx n x k, knn_dist2 n x k) with knn=True."""
+        import torch
+        X = _dev_f32(X, "X")
+        L = _dev_f32(L, "L", X.shape[1]).contiguous()
+        l = _dev_f32(l, "l", 2).contiguous()
+        n, d = X.shape
+        g = L.shape[0]
+        if out is None:
+            out = torch.empty((n, 2), dtype=torch.float32, device=X.device)
+        idx = dist = None
+        if knn:
+            idx = torch.empty((n, k), dtype=torch.int32, device=X.device)
+            dist = torch.empty((n, k), dtype=torch.float32, device=X.device)
+        p = esom_default_params(k=k, boost=boost, adjust=adjust, cutoff=cutoff, gravity=gravity,
+                                mode=mode, candidates=candidates)
+        _check(esom_embed(self.handle, X.data_ptr(), n, d, X.stride(0), L.data_ptr(),
+                          l.data_ptr(), g, p, out.data_ptr(),
+                          idx.data_ptr() if knn else 0, dist.data_ptr() if knn else 0,
+                          self._stream(stream)))
+        return (out, idx, dist) if knn else out
+
+    def landmark_update(self, X, L, l, kind="kmeans", alpha=0.1, sigma=1.0, nearest=None,
+                        counts=False, stream=None):
+        """Updates L in place (stream-ordered); returns the counts tensor if asked."""
+        import torch
+        X = _dev_f32(X, "X")
+        L = _dev_f32(L, "L", X.shape[1])
+        if not L.is_contiguous():
+            raise ValueError("L must be contiguous (it is updated in place)")
+        n, d = X.shape
+        g = L.shape[0]
+        lp = _dev_f32(l, "l", 2).contiguous().data_ptr() if l is not None else 0
+        cnt = torch.empty(g, dtype=torch.int32, device=X.device) if counts else None
+        np_ = 0
+        if nearest is not None:
+            if nearest.dtype != torch.int32 or not nearest.is_contiguous():
+                raise TypeError("nearest must be a contiguous int32 tensor")
+            np_ = nearest.data_ptr()
+        _check(esom_landmark_update(self.handle, X.data_ptr(), n, d, X.stride(0), L.data_ptr(), lp,
+                                    g, {"kmeans": 0, "som": 1}[kind], alpha, sigma, np_,
+                                    cnt.data_ptr() if counts else 0, self._stream(stream)))
+        return cnt
+
+    def set_timing(self, enable=True):
+        _check(esom_set_timing(self.handle, enable))
+
+    def sync(self, stream=None):
+        _check(esom_sync(self.handle, self._stream(stream)))
+
+    def stats(self, reset=False, stream=None):
+        return esom_get_stats(self.handle, self._stream(stream), reset)

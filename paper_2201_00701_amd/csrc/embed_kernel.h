@@ -151,16 +151,28 @@ __device__ __forceinline__ void screen_tile(const EmbedArgs &a, const PointOpera
 }
 
 template <int MODE, int DC, int KP>
-__global__ void __launch_bounds__(256) embed_main(EmbedArgs a) {
+__global__ void __launch_bounds__(512) embed_main(EmbedArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int DP = 16 * DC;
+    constexpr int RS = DP + 4;  // LDS row stride (floats): spreads rows over the banks
     const int lane = threadIdx.x & 63;
     const int wave = threadIdx.x >> 6;
     const int wpb = blockDim.x >> 6;
     const int h = lane >> 5;
     const int i32 = lane & 31;
     const int W = a.npair_tiles;
-    unsigned char *wsm = smem + (size_t)wave * wave_smem_bytes(KP, W);
+    // Optional block-wide copy of the landmark rows for exact rescoring.
+    float *rowsL = reinterpret_cast<float *>(smem);
+    const size_t rows_bytes = a.lds_rows ? (((size_t)a.g * RS * 4 + 255) & ~(size_t)255) : 0;
+    if (a.lds_rows) {
+        for (int e = threadIdx.x; e < a.g * (DP / 4); e += blockDim.x) {
+            const int j = e / (DP / 4), q = e % (DP / 4);
+            reinterpret_cast<float4 *>(rowsL + (size_t)j * RS)[q] =
+                reinterpret_cast<const float4 *>(a.Lpad + (size_t)j * DP)[q];
+        }
+        __syncthreads();
+    }
+    unsigned char *wsm = smem + rows_bytes + (size_t)wave * wave_smem_bytes(KP, W);
     unsigned *bitsL = reinterpret_cast<unsigned *>(wsm);
     float *nbD2 = reinterpret_cast<float *>(wsm);
     float *nbS = nbD2 + KP * 64;
@@ -304,17 +316,31 @@ __global__ void __launch_bounds__(256) embed_main(EmbedArgs a) {
                     const int t = 2 * tp + (pos >> 4);
                     const int r = pos & 15;
                     const int j = 32 * t + 8 * (r >> 2) + 4 * hh + (r & 3);
-                    const float4 *Lr = reinterpret_cast<const float4 *>(a.Lpad + (size_t)j * DP);
                     float acc = 0.f;
+                    if (a.lds_rows) {
+                        const float4 *Lr = reinterpret_cast<const float4 *>(rowsL + (size_t)j * RS);
 #pragma unroll
-                    for (int q = 0; q < DP / 4; ++q) {
-                        const float4 lv = Lr[q];
-                        const float e0 = x[4 * q] - lv.x, e1 = x[4 * q + 1] - lv.y;
-                        const float e2 = x[4 * q + 2] - lv.z, e3 = x[4 * q + 3] - lv.w;
-                        acc = fmaf(e0, e0, acc);
-                        acc = fmaf(e1, e1, acc);
-                        acc = fmaf(e2, e2, acc);
-                        acc = fmaf(e3, e3, acc);
+                        for (int q = 0; q < DP / 4; ++q) {
+                            const float4 lv = Lr[q];
+                            const float e0 = x[4 * q] - lv.x, e1 = x[4 * q + 1] - lv.y;
+                            const float e2 = x[4 * q + 2] - lv.z, e3 = x[4 * q + 3] - lv.w;
+                            acc = fmaf(e0, e0, acc);
+                            acc = fmaf(e1, e1, acc);
+                            acc = fmaf(e2, e2, acc);
+                            acc = fmaf(e3, e3, acc);
+                        }
+                    } else {
+                        const float4 *Lr = reinterpret_cast<const float4 *>(a.Lpad + (size_t)j * DP);
+#pragma unroll
+                        for (int q = 0; q < DP / 4; ++q) {
+                            const float4 lv = Lr[q];
+                            const float e0 = x[4 * q] - lv.x, e1 = x[4 * q + 1] - lv.y;
+                            const float e2 = x[4 * q + 2] - lv.z, e3 = x[4 * q + 3] - lv.w;
+                            acc = fmaf(e0, e0, acc);
+                            acc = fmaf(e1, e1, acc);
+                            acc = fmaf(e2, e2, acc);
+                            acc = fmaf(e3, e3, acc);
+                        }
                     }
                     insert_sorted<KP>(sk, rej, pack_key(acc, j));
                     ++m;

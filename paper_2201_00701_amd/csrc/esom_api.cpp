@@ -16,6 +16,7 @@ using namespace esom;
 struct esom_ctx {
     int device = 0;
     int num_cus = 0;
+    size_t lds_per_block = 65536;
     size_t budget = 0;  // 0 = unbounded
     size_t held = 0;    // bytes currently allocated
     unsigned long long *counters = nullptr;
@@ -225,7 +226,7 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
     a.counters = c->counters;
     a.knn_only = knn_only;
     if (pl.fast) {
-        e = launch_embed(a, P.mode, pl.kp, c->num_cus, s);
+        e = launch_embed(a, P.mode, pl.kp, c->num_cus, c->lds_per_block, s);
         if (e != hipSuccess) return hip_fail(e, "embed kernel launch");
         if (timed) (void)hipEventRecord(ev[2], s);
         e = launch_fallback(a, c->num_cus, s);
@@ -280,6 +281,7 @@ int esom_create(int device, size_t hbm_budget_bytes, esom_ctx **out) {
         return hip_fail(e, "hipGetDeviceProperties");
     }
     c->num_cus = prop.multiProcessorCount;
+    c->lds_per_block = prop.sharedMemPerBlock;
     int st = dev_alloc(c, reinterpret_cast<void **>(&c->counters),
                        sizeof(unsigned long long) * C_COUNT);
     if (st != ESOM_OK) {

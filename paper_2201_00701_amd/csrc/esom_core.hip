@@ -11,19 +11,25 @@ namespace esom {
 
 // ---------------------------------------------------------------- preparation
 
-// Centroid of the landmarks (FP64 sum, rounded to FP32), zero-padded to dp.
-// Also resets the per-call fallback list and the landmark norm maximum, and
-// counts the points of this call.
+// Centroid of the landmarks (FP64 sum, rounded to FP32), zero-padded to dp:
+// one block per dimension.  Block 0 also resets the per-call fallback list
+// and the landmark norm maximum, and counts the points of this call.
 __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
                               float *__restrict__ cent, float *__restrict__ lmax,
                               unsigned long long *__restrict__ counters, long long n_points) {
-    for (int t = threadIdx.x; t < dp; t += blockDim.x) {
-        double s = 0.0;
-        if (t < d)
-            for (int j = 0; j < g; ++j) s += (double)L[(size_t)j * d + t];
-        cent[t] = t < d ? (float)(s / (double)g) : 0.f;
+    __shared__ double red[256];
+    const int t = blockIdx.x;
+    double s = 0.0;
+    if (t < d)
+        for (int j = threadIdx.x; j < g; j += blockDim.x) s += (double)L[(size_t)j * d + t];
+    red[threadIdx.x] = s;
+    __syncthreads();
+    for (int o = blockDim.x / 2; o > 0; o >>= 1) {
+        if ((int)threadIdx.x < o) red[threadIdx.x] += red[threadIdx.x + o];
+        __syncthreads();
     }
-    if (threadIdx.x == 0) {
+    if (threadIdx.x == 0) cent[t] = t < d ? (float)(red[0] / (double)g) : 0.f;
+    if (t == 0 && threadIdx.x == 0) {
         *lmax = 0.f;
         counters[C_FB_LEN] = 0ull;
         counters[C_POINTS] += (unsigned long long)n_points;
@@ -82,8 +88,8 @@ __global__ void prep_pairs(const float *__restrict__ L, int g, int d, float *__r
 
 hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long long *counters,
                        long long n_points, hipStream_t s) {
-    hipLaunchKernelGGL(prep_centroid, dim3(1), dim3(256), 0, s, L, P.g, P.d, P.dp, P.cent, P.lmax,
-                       counters, n_points);
+    hipLaunchKernelGGL(prep_centroid, dim3(P.dp), dim3(256), 0, s, L, P.g, P.d, P.dp, P.cent,
+                       P.lmax, counters, n_points);
     const int gpad = P.ntiles * TILE;
     hipLaunchKernelGGL(prep_landmarks, dim3((gpad + 255) / 256), dim3(256), 0, s, L, P.g, gpad, P.d,
                        P.dp, mode, P.cent, P.A, P.norms, P.Lpad, P.lmax);
@@ -95,21 +101,47 @@ hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long lo
 
 // ---------------------------------------------------------------- exact FP64 path
 
-// Recomputes points exactly in FP64: full k-nearest scan with (distance,
-// index) order, scores, every pair's segment projection from the
-// coordinates, Cramer's rule; the centroid for degenerate neighbourhoods.
-// all_points = 1 processes every point (shapes outside the fast kernels).
+// (distance, index) lexicographic minimum across the wavefront.
+__device__ __forceinline__ void wave_argmin(double &v, int &j) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) {
+        const double ov = __shfl_xor(v, o);
+        const int oj = __shfl_xor(j, o);
+        if (ov < v || (ov == v && oj < j)) {
+            v = ov;
+            j = oj;
+        }
+    }
+}
+
+__device__ __forceinline__ double wave_sum(double v) {
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) v += __shfl_xor(v, o);
+    return v;
+}
+
+// Recomputes points exactly in FP64, one wavefront (block of 64) per point:
+// all g distances from the coordinates into LDS, the k (+1) nearest by
+// repeated wave-wide (distance, index) minima, the scores, every pair's
+// segment projection from the coordinates spread over the lanes, and
+// Cramer's rule; the centroid of the neighbours for degenerate
+// neighbourhoods.  all_points = 1 processes every point (shapes outside the
+// fast kernels), otherwise the fast kernel's list.
 __global__ void __launch_bounds__(64) embed_exact(EmbedArgs a, int all_points) {
+    extern __shared__ __align__(16) unsigned char esm[];
+    double *dist = reinterpret_cast<double *>(esm);        // g
+    double *xs = dist + a.g;                                // d
+    double *sel_d = xs + a.d;                               // k + 1
+    double *sc = sel_d + (ESOM_MAX_K + 1);                  // k
+    int *sel_j = reinterpret_cast<int *>(sc + ESOM_MAX_K);  // k + 1
+    const int lane = threadIdx.x;
     const long long cnt = all_points
                               ? a.n
                               : (long long)min(a.counters[C_FB_LEN], (unsigned long long)a.n);
+    const int k = a.k;
+    const int m = k + 1 <= a.g ? k + 1 : a.g;
     unsigned long long n_fb = 0, n_unc = 0, n_tie = 0, n_ill = 0, n_deg = 0;
-    double dd[ESOM_MAX_K + 1];
-    int nb[ESOM_MAX_K + 1];
-    double dl[ESOM_MAX_K], sc[ESOM_MAX_K];
-    const int m = a.k + 1 <= a.g ? a.k + 1 : a.g;
-    for (long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x; e < cnt;
-         e += (long long)gridDim.x * blockDim.x) {
+    for (long long e = blockIdx.x; e < cnt; e += gridDim.x) {
         const long long pi = all_points ? e : (long long)a.fb_list[e];
         const unsigned reason = all_points ? 0u : (unsigned)a.fb_reason[e];
         ++n_fb;
@@ -117,119 +149,143 @@ __global__ void __launch_bounds__(64) embed_exact(EmbedArgs a, int all_points) {
         n_tie += (reason & R_NEARTIE) ? 1 : 0;
         n_ill += (reason & R_ILLCOND) ? 1 : 0;
         const float *xr = a.X + pi * a.ldx;
-        for (int q = 0; q < m; ++q) {
-            dd[q] = INFINITY;
-            nb[q] = -1;
-        }
-        for (int j = 0; j < a.g; ++j) {
+        for (int q = lane; q < a.d; q += 64) xs[q] = (double)xr[q];
+        __syncthreads();
+        for (int j = lane; j < a.g; j += 64) {
             const float *Lj = a.Lpad + (size_t)j * a.dp;
             double s = 0.0;
             for (int q = 0; q < a.d; ++q) {
-                const double df = (double)xr[q] - (double)Lj[q];
-                s += df * df;
+                const double df = xs[q] - (double)Lj[q];
+                s = fma(df, df, s);
             }
-            if (nb[m - 1] >= 0 && !(s < dd[m - 1])) continue;  // j ascends: ties keep the earlier
-            int pos = m - 1;
-            while (pos > 0 && (nb[pos - 1] < 0 || s < dd[pos - 1])) {
-                dd[pos] = dd[pos - 1];
-                nb[pos] = nb[pos - 1];
-                --pos;
-            }
-            dd[pos] = s;
-            nb[pos] = j;
+            dist[j] = s;
         }
-        const int k = a.k;
-        if (a.knn_idx)
-            for (int q = 0; q < k; ++q) a.knn_idx[pi * k + q] = nb[q];
-        if (a.knn_d2)
-            for (int q = 0; q < k; ++q) a.knn_d2[pi * k + q] = (float)dd[q];
-        if (a.knn_only) continue;
-        if (nb[k - 1] < 0) {  // non-finite input: no ordered neighbours
-            a.out[2 * pi] = NAN;
-            a.out[2 * pi + 1] = NAN;
-            continue;
-        }
-
-        // scores
-        for (int q = 0; q < k; ++q) dl[q] = sqrt(dd[q]);
-        bool degenerate = dl[0] == dl[k - 1];
-        double ssum = 0.0;
-        if (!degenerate) {
-            double W = 0.0, mu = 0.0;
-            for (int q = 0; q < k; ++q) {
-                W += 1.0 / (q + 1);
-                mu += dl[q] / (q + 1);
-            }
-            mu /= W;
-            double var = 0.0;
-            for (int q = 0; q < k; ++q) var += (dl[q] - mu) * (dl[q] - mu) / (q + 1);
-            var /= W;
-            const bool flat = !(var > 1e-30 * mu * mu);
-            for (int q = 0; q < k; ++q) {
-                const double ev = flat ? 1.0 : exp((double)a.boost * (mu - dl[q]) / sqrt(var));
-                const double cv = a.use_cutoff ? 1.0 - exp((double)a.cutoff * (dl[q] / dl[k - 1] - 1.0))
-                                               : 1.0;
-                sc[q] = ev * cv;
-                ssum += sc[q];
-            }
-        }
-        // pairs: D_uv from the coordinates (FP64)
-        double M00 = 0.0, M01 = 0.0, M11 = 0.0, r0 = 0.0, r1 = 0.0;
-        if (!degenerate) {
-            for (int qi = 0; qi < k; ++qi) {
-                const int u = nb[qi];
-                const float *Lu = a.Lpad + (size_t)u * a.dp;
-                const double lux = a.l2d[2 * u], luy = a.l2d[2 * u + 1];
-                for (int qj = qi + 1; qj < k; ++qj) {
-                    const int v = nb[qj];
-                    const float *Lv = a.Lpad + (size_t)v * a.dp;
-                    double HH = 0.0, xH = 0.0;
-                    for (int q = 0; q < a.d; ++q) {
-                        const double H = (double)Lv[q] - (double)Lu[q];
-                        HH += H * H;
-                        xH += ((double)xr[q] - (double)Lu[q]) * H;
-                    }
-                    if (HH == 0.0) continue;
-                    const double D = xH / HH;
-                    const double hx = (double)a.l2d[2 * v] - lux, hy = (double)a.l2d[2 * v + 1] - luy;
-                    const double hh = hx * hx + hy * hy;
-                    if (hh == 0.0) continue;
-                    const double qw = sc[qi] * sc[qj] * pow(hh, -(double)a.adjust);
-                    const double rhs = D + (hx * lux + hy * luy) / hh;
-                    M00 += qw * hx * hx / hh;
-                    M01 += qw * hx * hy / hh;
-                    M11 += qw * hy * hy / hh;
-                    r0 += qw * hx * rhs;
-                    r1 += qw * hy * rhs;
+        __syncthreads();
+        // m smallest by (distance, index); taken entries become NaN (never minimal)
+        bool bad = false;
+        for (int r = 0; r < m; ++r) {
+            double bv = INFINITY;
+            int bj = 0x7fffffff;
+            for (int j = lane; j < a.g; j += 64) {
+                const double v = dist[j];
+                if (v < bv || (v == bv && j < bj)) {
+                    bv = v;
+                    bj = j;
                 }
             }
-            for (int q = 0; q < k; ++q) {
-                const double gs = (double)a.gravity * sc[q];
-                M00 += gs;
-                M11 += gs;
-                r0 += gs * a.l2d[2 * nb[q]];
-                r1 += gs * a.l2d[2 * nb[q] + 1];
+            wave_argmin(bv, bj);
+            if (bj == 0x7fffffff) bad = true;
+            if (lane == 0) {
+                sel_d[r] = bv;
+                sel_j[r] = bj;
+                if (bj != 0x7fffffff) dist[bj] = NAN;
             }
+            __syncthreads();
         }
-        const double det = M00 * M11 - M01 * M01;
-        double px, py;
-        if (degenerate || !(ssum > 0.0) || !(det > 0.0)) {
-            double cx = 0.0, cy = 0.0;
-            for (int q = 0; q < k; ++q) {
-                cx += a.l2d[2 * nb[q]];
-                cy += a.l2d[2 * nb[q] + 1];
+        if (lane < k) {
+            if (a.knn_idx) a.knn_idx[pi * k + lane] = bad ? -1 : sel_j[lane];
+            if (a.knn_d2) a.knn_d2[pi * k + lane] = (float)sel_d[lane];
+        }
+        if (a.knn_only) continue;
+        if (bad) {
+            if (lane == 0) {
+                a.out[2 * pi] = NAN;
+                a.out[2 * pi + 1] = NAN;
             }
-            px = cx / k;
-            py = cy / k;
-            ++n_deg;
-        } else {
-            px = (r0 * M11 - M01 * r1) / det;
-            py = (M00 * r1 - M01 * r0) / det;
+            continue;
         }
-        a.out[2 * pi] = (float)px;
-        a.out[2 * pi + 1] = (float)py;
+        // scores (every lane computes the neighbourhood statistics)
+        const double dl0 = sqrt(sel_d[0]), dlk = sqrt(sel_d[k - 1]);
+        const bool degenerate = dl0 == dlk;
+        double W = 0.0, mu = 0.0;
+        for (int q = 0; q < k; ++q) {
+            W += 1.0 / (q + 1);
+            mu += sqrt(sel_d[q]) / (q + 1);
+        }
+        mu /= W;
+        double var = 0.0;
+        for (int q = 0; q < k; ++q) {
+            const double t = sqrt(sel_d[q]) - mu;
+            var += t * t / (q + 1);
+        }
+        var /= W;
+        const bool flat = !(var > 1e-30 * mu * mu);
+        if (lane < k) {
+            const double dq = sqrt(sel_d[lane]);
+            const double ev = flat ? 1.0 : exp((double)a.boost * (mu - dq) / sqrt(var));
+            const double cv = a.use_cutoff ? 1.0 - exp((double)a.cutoff * (dq / dlk - 1.0)) : 1.0;
+            sc[lane] = degenerate ? 0.0 : ev * cv;
+        }
+        __syncthreads();
+        // pairs spread over the lanes
+        double M00 = 0.0, M01 = 0.0, M11 = 0.0, r0 = 0.0, r1 = 0.0, ssum = 0.0;
+        const int npair = k * (k - 1) / 2;
+        for (int p = lane; p < npair && !degenerate; p += 64) {
+            int qi = 0, rem = p;
+            while (rem >= k - 1 - qi) {
+                rem -= k - 1 - qi;
+                ++qi;
+            }
+            const int qj = qi + 1 + rem;
+            const int u = sel_j[qi], v = sel_j[qj];
+            const float *Lu = a.Lpad + (size_t)u * a.dp;
+            const float *Lv = a.Lpad + (size_t)v * a.dp;
+            double HH = 0.0, xH = 0.0;
+            for (int q = 0; q < a.d; ++q) {
+                const double H = (double)Lv[q] - (double)Lu[q];
+                HH = fma(H, H, HH);
+                xH = fma(xs[q] - (double)Lu[q], H, xH);
+            }
+            if (HH == 0.0) continue;
+            const double D = xH / HH;
+            const double lux = a.l2d[2 * u], luy = a.l2d[2 * u + 1];
+            const double hx = (double)a.l2d[2 * v] - lux, hy = (double)a.l2d[2 * v + 1] - luy;
+            const double hh = hx * hx + hy * hy;
+            if (hh == 0.0) continue;
+            const double qw = sc[qi] * sc[qj] * pow(hh, -(double)a.adjust);
+            const double rhs = D + (hx * lux + hy * luy) / hh;
+            M00 += qw * hx * hx / hh;
+            M01 += qw * hx * hy / hh;
+            M11 += qw * hy * hy / hh;
+            r0 += qw * hx * rhs;
+            r1 += qw * hy * rhs;
+        }
+        if (lane < k && !degenerate) {
+            const double gs = (double)a.gravity * sc[lane];
+            M00 += gs;
+            M11 += gs;
+            r0 += gs * a.l2d[2 * sel_j[lane]];
+            r1 += gs * a.l2d[2 * sel_j[lane] + 1];
+            ssum += sc[lane];
+        }
+        M00 = wave_sum(M00);
+        M01 = wave_sum(M01);
+        M11 = wave_sum(M11);
+        r0 = wave_sum(r0);
+        r1 = wave_sum(r1);
+        ssum = wave_sum(ssum);
+        if (lane == 0) {
+            const double det = M00 * M11 - M01 * M01;
+            double px, py;
+            if (degenerate || !(ssum > 0.0) || !(det > 0.0)) {
+                double cx = 0.0, cy = 0.0;
+                for (int q = 0; q < k; ++q) {
+                    cx += a.l2d[2 * sel_j[q]];
+                    cy += a.l2d[2 * sel_j[q] + 1];
+                }
+                px = cx / k;
+                py = cy / k;
+                ++n_deg;
+            } else {
+                px = (r0 * M11 - M01 * r1) / det;
+                py = (M00 * r1 - M01 * r0) / det;
+            }
+            a.out[2 * pi] = (float)px;
+            a.out[2 * pi + 1] = (float)py;
+        }
+        __syncthreads();
     }
-    if (n_fb) {
+    if (lane == 0 && n_fb) {
         atomicAdd(&a.counters[all_points ? C_SLOW : C_FALLBACK], n_fb);
         if (n_unc) atomicAdd(&a.counters[C_UNCERT], n_unc);
         if (n_tie) atomicAdd(&a.counters[C_NEARTIE], n_tie);
@@ -238,16 +294,21 @@ __global__ void __launch_bounds__(64) embed_exact(EmbedArgs a, int all_points) {
     }
 }
 
+static size_t exact_smem(const EmbedArgs &a) {
+    return sizeof(double) * ((size_t)a.g + a.d + 2 * ESOM_MAX_K + 1) + sizeof(int) * (ESOM_MAX_K + 1);
+}
+
 hipError_t launch_fallback(const EmbedArgs &a, int num_cus, hipStream_t s) {
-    hipLaunchKernelGGL(embed_exact, dim3(num_cus * 4), dim3(64), 0, s, a, 0);
+    // The list length is only known on the device: a fixed grid loops over it.
+    hipLaunchKernelGGL(embed_exact, dim3(num_cus * 4), dim3(64), exact_smem(a), s, a, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, hipStream_t s) {
-    long long blocks = (a.n + 63) / 64;
+    long long blocks = a.n;
     if (blocks > (long long)num_cus * 16) blocks = (long long)num_cus * 16;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(embed_exact, dim3((unsigned)blocks), dim3(64), 0, s, a, 1);
+    hipLaunchKernelGGL(embed_exact, dim3((unsigned)blocks), dim3(64), exact_smem(a), s, a, 1);
     return hipGetLastError();
 }
 
@@ -263,13 +324,25 @@ hipError_t launch_main_m1_kp8(const EmbedArgs &, int, int, size_t, int, hipStrea
 hipError_t launch_main_m1_kp16(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m1_kp32(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 
-hipError_t launch_embed(const EmbedArgs &a, int mode, int kp, int num_cus, hipStream_t s) {
+hipError_t launch_embed(const EmbedArgs &a0, int mode, int kp, int num_cus, size_t lds_per_block,
+                        hipStream_t s) {
+    EmbedArgs a = a0;
     const int dc = a.dp / 16;
-    const int wsm = wave_smem_bytes(kp, a.npair_tiles);
-    int wpb = 65536 / wsm;
-    if (wpb > 4) wpb = 4;
-    if (wpb < 1) wpb = 1;
-    const size_t smem = (size_t)wpb * wsm;
+    const size_t wsm = (size_t)wave_smem_bytes(kp, a.npair_tiles);
+    const size_t rows = ((size_t)a.g * (a.dp + 4) * 4 + 255) & ~(size_t)255;
+    // Stage the landmark rows in LDS when 8 waves still fit beside them,
+    // otherwise rescore from global memory with 4-wave blocks.
+    int wpb;
+    if (rows + 8 * wsm <= lds_per_block) {
+        a.lds_rows = 1;
+        wpb = 8;
+    } else {
+        a.lds_rows = 0;
+        wpb = (int)(lds_per_block / wsm);
+        if (wpb > 4) wpb = 4;
+        if (wpb < 1) wpb = 1;
+    }
+    const size_t smem = (a.lds_rows ? rows : 0) + (size_t)wpb * wsm;
     const int block = 64 * wpb;
     if (mode == 0) {
         if (kp == 8) return launch_main_m0_kp8(a, dc, block, smem, num_cus, s);

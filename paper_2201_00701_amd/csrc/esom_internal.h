@@ -4,7 +4,7 @@
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
-#include "../../include/esom.h"
+#include "esom.h"
 
 namespace esom {
 
@@ -74,12 +74,14 @@ struct EmbedArgs {
     uint8_t *fb_reason;
     unsigned long long *counters;
     int knn_only;  // 1: only write knn outputs (no projection)
+    int lds_rows;  // 1: the block stages Lpad in LDS (row stride dp + 4 floats)
 };
 
 // Launchers (esom_embed.hip).
 hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long long *counters,
                        long long n_points, hipStream_t s);
-hipError_t launch_embed(const EmbedArgs &a, int mode, int kp, int num_cus, hipStream_t s);
+hipError_t launch_embed(const EmbedArgs &a, int mode, int kp, int num_cus, size_t lds_per_block,
+                        hipStream_t s);
 hipError_t launch_fallback(const EmbedArgs &a, int num_cus, hipStream_t s);
 hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, hipStream_t s);
 

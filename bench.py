@@ -53,6 +53,106 @@ def cpu_baseline(w, seconds):
                       % (n, len(w.X), dt)}
 
 
+def serve_mix(n_requests=2000, warmup=200, rate=200.0, budget=8 << 30, slots=4, seed=5,
+              base_n=1_000_000):
+    """Serving mix: Poisson arrivals; N log-uniform in [1e3, 1e6]; D in {16, 32, 48};
+    g in {100, 400, 1024} (10x10, 20x20, 32x32 grids); k in {8, 16, 20}; 10% of the
+    requests re-embed a resident dataset after moving 1-5 of its 2-D landmarks by
+    N(0, 0.5^2).  New points are uploaded from pinned host memory within the
+    request.  Latency = result in host memory minus scheduled arrival."""
+    import threading
+
+    import numpy as np
+    import torch
+
+    from paper_2201_00701_amd import esom, synth
+
+    rng = np.random.default_rng(seed)
+    Ds, Gs, Ks = (16, 32, 48), (100, 400, 1024), (8, 16, 20)
+    grid = {100: 10, 400: 20, 1024: 32}
+    base, LM = {}, {}
+    for D in Ds:
+        X = synth.mixture(base_n, D, 30, seed=seed * 100 + D)
+        pin = torch.empty((base_n, D), dtype=torch.float32, pin_memory=True).numpy()
+        pin[:] = X
+        base[D] = pin
+        for g in Gs:
+            LM[(D, g)] = synth.landmarks_from_data(X, g, seed=seed * 100 + D + g)
+    srv = esom.Server(0, budget, slots)
+    resident = {}
+    for D in Ds:
+        g = int(rng.choice(Gs))
+        k = int(rng.choice(Ks))
+        n = 100_000
+        resident[D] = {"id": srv.put(np.ascontiguousarray(base[D][:n])), "g": g, "k": k, "n": n,
+                       "l": synth.grid2d(g, grid[g]).copy(),
+                       "out": np.empty((n, 2), np.float32)}
+    total = warmup + n_requests
+    arrivals = np.cumsum(rng.exponential(1.0 / rate, total))
+    plan = []
+    for i in range(total):
+        if rng.random() < 0.1:
+            D = int(rng.choice(Ds))
+            plan.append(("edit", D, int(rng.integers(1, 6))))
+        else:
+            N = int(round(np.exp(rng.uniform(np.log(1e3), np.log(1e6)))))
+            plan.append(("new", int(rng.choice(Ds)), int(rng.choice(Gs)), int(rng.choice(Ks)), N,
+                         int(rng.integers(0, base_n - N + 1))))
+    rids = [None] * total
+    infos = [None] * total
+    outs = {}
+    done_evt = threading.Event()
+
+    def waiter():
+        for i in range(total):
+            while rids[i] is None:
+                time.sleep(0.0002)
+            infos[i] = srv.wait(rids[i], -1)
+        done_evt.set()
+
+    th = threading.Thread(target=waiter, daemon=True)
+    off = srv.stats()["now_ms"] - time.perf_counter() * 1e3
+    t_start = time.perf_counter() + 0.05
+    th.start()
+    for i, item in enumerate(plan):
+        t_arr = t_start + arrivals[i]
+        while True:
+            dt = t_arr - time.perf_counter()
+            if dt <= 0:
+                break
+            time.sleep(min(dt, 0.001))
+        if item[0] == "edit":
+            _, D, m = item
+            r = resident[D]
+            moved = rng.choice(r["g"], m, replace=False)
+            r["l"][moved] += rng.normal(0, 0.5, (m, 2)).astype(np.float32)
+            rids[i] = srv.submit(LM[(D, r["g"])], np.ascontiguousarray(r["l"]), k=r["k"],
+                                 mode="bf16", dataset=r["id"], out=r["out"])
+        else:
+            _, D, g, k, N, o = item
+            X = base[D][o:o + N]
+            outs[i] = np.empty((N, 2), np.float32)
+            rids[i] = srv.submit(LM[(D, g)], synth.grid2d(g, grid[g]), k=min(k, g), mode="bf16",
+                                 X=X, out=outs[i])
+    done_evt.wait()
+    st = srv.stats()
+    srv.close()
+    lat, pts = [], 0
+    for i in range(warmup, total):
+        lat.append(infos[i]["done_ms"] - ((t_start + arrivals[i]) * 1e3 + off))
+        pts += infos[i]["n"]
+    lat = np.array(lat)
+    first = (t_start + arrivals[warmup]) * 1e3 + off
+    last = max(infos[i]["done_ms"] for i in range(warmup, total))
+    return {"requests": n_requests, "warmup_requests": warmup, "rate_req_s": rate,
+            "p50_ms": float(np.percentile(lat, 50)), "p99_ms": float(np.percentile(lat, 99)),
+            "max_ms": float(lat.max()), "points_per_s": pts / ((last - first) * 1e-3),
+            "cache_hits": int(sum(infos[i]["cache_hit"] for i in range(warmup, total))),
+            "graph_replays": int(sum(infos[i]["graph_replay"] for i in range(warmup, total))),
+            "slots": slots, "budget_gib": budget / float(1 << 30), "peak_gib": st["peak_bytes"] / float(1 << 30),
+            "mode": "bf16"}
+
+
 def main():
     ap = argparse.ArgumentParser(description=__doc__)
     ap.add_argument("--gpus", type=int, default=1)
@@ -62,6 +162,8 @@ def main():
     ap.add_argument("--modes", default="bf16,fp32")
     ap.add_argument("--cpu-seconds", type=float, default=8.0)
     ap.add_argument("--no-cpu-baseline", action="store_true")
+    ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--serve-requests", type=int, default=2000)
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the projection is data-parallel over points and this "
@@ -146,6 +248,12 @@ def main():
         "roofline": results[head]["roofline"],
         "modes": results,
     }
+    if not args.no_serve:
+        print("bench: serving mix (%d requests)" % args.serve_requests, file=sys.stderr, flush=True)
+        line["serving"] = serve_mix(n_requests=args.serve_requests)
+        print("bench: serving p50 %.2f ms p99 %.2f ms" % (line["serving"]["p50_ms"],
+                                                          line["serving"]["p99_ms"]),
+              file=sys.stderr, flush=True)
     if not args.no_cpu_baseline:
         line["cpu_baseline"] = cpu_baseline(w, args.cpu_seconds)
     print(json.dumps(line), flush=True)

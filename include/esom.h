@@ -170,6 +170,80 @@ int esom_get_stats(esom_ctx *ctx, void *stream, esom_stats *stats, int32_t reset
  * ms_exact.  Timing serialises nothing but costs six event records per call. */
 int esom_set_timing(esom_ctx *ctx, int32_t enable);
 
+/* ---------------------------------------------------------------- serving
+ * Continuous batching of embed requests on one GPU (the interactive loop in
+ * which the paper re-projects all points every frame while the user edits
+ * landmarks; Sections "User supervision and model interaction" and
+ * "Accelerated EmbedSOM performance").  Requests with uneven n, d, g and k are
+ * queued in arrival order and admitted as soon as one of the server's slots
+ * is free and the request's device-memory footprint fits the budget beside
+ * the resident datasets and the memory the other slots hold; admitted
+ * requests run concurrently on separate HIP streams.  Each request computes
+ * exactly what esom_embed computes for the same inputs (results do not depend
+ * on what else runs).  Resident datasets cache their last k-nearest result:
+ * a request that changes only 2-D landmarks reuses it and skips the distance
+ * screen.  Repeated identical frames on a slot are replayed from a captured
+ * hipGraph.  All host pointers below are host memory; the server owns its
+ * device and pinned staging memory.  Every submitted request must be waited
+ * for (esom_serve_wait) to release its bookkeeping. */
+typedef struct esom_server esom_server;
+
+typedef struct {
+    double submit_ms;      /* host steady-clock times, ms since esom_serve_create */
+    double start_ms;       /* admitted to a slot */
+    double done_ms;        /* result copied to out_host */
+    int64_t n;             /* points */
+    int32_t cache_hit;     /* 1: projected from the dataset's cached k nearest */
+    int32_t graph_replay;  /* 1: replayed a captured frame */
+    int32_t status;        /* ESOM_OK or the error of the device path */
+    int32_t reserved;
+} esom_request_info;
+
+typedef struct {
+    int64_t completed, failed, rejected, points, cache_hits, graph_replays;
+    int64_t queued, in_flight, slots;
+    int64_t budget_bytes, resident_bytes, held_bytes, peak_bytes;
+    double now_ms;
+} esom_serve_stats;
+
+/* Creates a server on `device` with `n_slots` (1..16) concurrent request
+ * slots; hbm_budget_bytes bounds datasets + caches + slot memory (0 = none). */
+int esom_serve_create(int device, size_t hbm_budget_bytes, int32_t n_slots, esom_server **out);
+
+/* Finishes every queued and running request, then frees everything. */
+void esom_serve_destroy(esom_server *srv);
+
+/* Copies n x d host floats (row-major) into a resident device dataset
+ * (synchronous).  ESOM_ENOMEM if it does not fit the budget. */
+int esom_serve_dataset_put(esom_server *srv, const float *X_host, int64_t n, int32_t d,
+                           uint64_t *dataset_id);
+
+/* Drops a resident dataset; its memory is freed once the requests that use it
+ * have finished.  ESOM_ENOTFOUND for an unknown id. */
+int esom_serve_dataset_drop(esom_server *srv, uint64_t dataset_id);
+
+/* Queues one embed request and returns at once.
+ *   dataset_id != 0: embed that resident dataset (X_host must be NULL; n, d ignored);
+ *   dataset_id == 0: X_host (n x d host floats, pinned for best latency, valid
+ *                    until the request completes) is uploaded with the request.
+ *   L_hd_host (g x d) and L_2d_host (g x 2) are copied before the call returns.
+ *   out_host (n x 2 floats) is written before esom_serve_wait reports success.
+ * Errors: ESOM_EINVAL (arguments, as for esom_embed), ESOM_ENOTFOUND (dataset),
+ * ESOM_ENOMEM (the footprint can never fit the budget beside the residents). */
+int esom_serve_submit(esom_server *srv, uint64_t dataset_id, const float *X_host, int64_t n,
+                      int32_t d, const float *L_hd_host, const float *L_2d_host, int32_t g,
+                      const esom_params *params, float *out_host, uint64_t *request_id);
+
+/* Waits up to timeout_ms (< 0: forever) for a request.  ESOM_OK: out_host holds
+ * the result and *info (may be NULL) its timing; the id is then forgotten.
+ * ESOM_ETIMEOUT: still pending.  ESOM_ENOTFOUND: unknown id.  Other codes: the
+ * request failed on the device path (the id is forgotten). */
+int esom_serve_wait(esom_server *srv, uint64_t request_id, int32_t timeout_ms,
+                    esom_request_info *info);
+
+/* Snapshot of the server's counters. */
+int esom_serve_get_stats(esom_server *srv, esom_serve_stats *stats);
+
 #ifdef __cplusplus
 }
 #endif

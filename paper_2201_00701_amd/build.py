@@ -22,7 +22,8 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
          "-Xclang", "-target-feature", "-Xclang", "-packed-fp32-ops",
          "-I", INCLUDE, "-I", CSRC]
 
-UNITS = [("esom_core.hip", []), ("esom_update.hip", []), ("esom_api.cpp", ["-x", "hip"])]
+UNITS = [("esom_core.hip", []), ("esom_update.hip", []), ("esom_api.cpp", ["-x", "hip"]),
+         ("esom_serve.cpp", ["-x", "hip"])]
 for mode in (0, 1):
     for kp in (8, 16, 32):
         UNITS.append(("embed_inst.hip", ["-DINST_MODE=%d" % mode, "-DINST_KP=%d" % kp]))
@@ -52,7 +53,7 @@ def build(jobs: int | None = None, verbose: bool = False) -> str:
     with cf.ThreadPoolExecutor(jobs) as ex:
         objs = list(ex.map(_compile, UNITS))
     tmp = LIB + ".tmp%d" % os.getpid()
-    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs
+    cmd = ["hipcc", "-shared", "-fPIC", "--offload-arch=" + ARCH, "-o", tmp] + objs + ["-lpthread"]
     r = subprocess.run(cmd, capture_output=True, text=True)
     if r.returncode != 0:
         raise RuntimeError("link failed:\n" + r.stdout + r.stderr)

@@ -150,6 +150,192 @@ __device__ __forceinline__ void screen_tile(const EmbedArgs &a, const PointOpera
     }
 }
 
+// Phase C for one point (lane): scores from the k sorted distances, the pair
+// terms, the FP64 2x2 solve and the output store.  sk holds the k nearest as
+// packed (delta^2, index) keys, ascending.  Returns the accumulated fallback
+// reasons; the output is written only when there is none.
+template <int KP>
+__device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const double (&sk)[KP],
+                                                  int lane, bool valid, long long pi, unsigned reason,
+                                                  float *nbD2, float *nbS, unsigned short *nbI) {
+    float d2q[KP], dl[KP], sq[KP], lxq[KP], lyq[KP];
+    int jq[KP];
+    float mu = 0.f;
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+        d2q[q] = (q < a.k) ? key_d2(sk[q]) : 0.f;
+        jq[q] = (q < a.k) ? key_idx(sk[q]) : 0;
+        dl[q] = sqrtf(d2q[q]);
+        if (q < a.k) mu = fmaf(dl[q], 1.f / (float)(q + 1), mu);
+    }
+    float d2k = d2q[0];
+#pragma unroll
+    for (int q = 0; q < KP; ++q)
+        if (q == a.k - 1) d2k = d2q[q];
+    mu /= a.Wk;
+    float var = 0.f;
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+        if (q < a.k) {
+            const float e = dl[q] - mu;
+            var = fmaf(e * e, 1.f / (float)(q + 1), var);
+        }
+    }
+    var /= a.Wk;
+    const float dk = sqrtf(d2k);
+    const bool degenerate = d2q[0] == d2k;
+    const bool flat = !(var > 1e-30f * mu * mu);
+    const float isig = flat ? 0.f : a.boost * rsqrtf(var);
+    if (degenerate) reason |= R_DEGEN;
+    const float ox = a.l2d[2 * jq[0]], oy = a.l2d[2 * jq[0] + 1];
+    float ssum = 0.f;
+    float M00 = 0.f, M01 = 0.f, M11 = 0.f, r0 = 0.f, r1 = 0.f;
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+        const float2 lv = reinterpret_cast<const float2 *>(a.l2d)[jq[q]];
+        lxq[q] = lv.x - ox;
+        lyq[q] = lv.y - oy;
+    }
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+        sq[q] = 0.f;
+        if (q < a.k) {
+            const float e = flat ? 1.f : __expf((mu - dl[q]) * isig);
+            const float c = a.use_cutoff ? -expm1f(a.cutoff * (dl[q] - dk) / dk) : 1.f;
+            sq[q] = degenerate ? 0.f : e * c;
+            ssum += sq[q];
+            const float gs = a.gravity * sq[q];
+            M00 += gs;
+            M11 += gs;
+            r0 = fmaf(gs, lxq[q], r0);
+            r1 = fmaf(gs, lyq[q], r1);
+        }
+    }
+    if (!(ssum > 0.f)) reason |= R_DEGEN;
+
+    // pairs (i < j among the neighbours with non-zero score)
+    const bool unit_adjust = a.adjust == 1.0f;
+    bool ill = false;
+    auto pair_term = [&](float d2i, float si, float lxi, float lyi, float d2j, float sj, float lxj,
+                         float lyj, float inv) {
+        const float hx = lxj - lxi, hy = lyj - lyi;
+        const float hh = fmaf(hx, hx, hy * hy);
+        const bool skip = inv < 0.f || hh == 0.f;
+        const float hs = skip ? 1.f : hh;
+        if (!skip && fmaxf(d2i, d2j) * inv > ILL_PAIR) ill = true;
+        const float D = fmaf(d2i - d2j, inv, 0.5f);
+        const float ihh = 1.f / hs;
+        const float q = skip ? 0.f : si * sj * (unit_adjust ? ihh : exp2f(-a.adjust * __log2f(hs)));
+        const float qh = q * ihh;
+        const float t = fmaf(D, hs, fmaf(hx, lxi, hy * lyi));
+        const float qhx = qh * hx, qhy = qh * hy;
+        M00 = fmaf(qhx, hx, M00);
+        M01 = fmaf(qhx, hy, M01);
+        M11 = fmaf(qhy, hy, M11);
+        r0 = fmaf(qhx, t, r0);
+        r1 = fmaf(qhy, t, r1);
+    };
+    if constexpr (KP <= 16) {
+        // neighbour data in registers; each row of pair-table loads is issued together
+#pragma unroll
+        for (int qi = 0; qi < KP - 1; ++qi) {
+            if (qi < a.kact - 1) {
+                const float *invrow = a.inv2 + (size_t)jq[qi] * a.g;
+                float inv[KP];
+#pragma unroll
+                for (int qj = qi + 1; qj < KP; ++qj) inv[qj] = (qj < a.kact) ? invrow[jq[qj]] : -1.f;
+#pragma unroll
+                for (int qj = qi + 1; qj < KP; ++qj)
+                    if (qj < a.kact)
+                        pair_term(d2q[qi], sq[qi], lxq[qi], lyq[qi], d2q[qj], sq[qj], lxq[qj], lyq[qj],
+                                  inv[qj]);
+            }
+        }
+    } else {
+        // larger neighbourhoods: neighbour data through LDS, inner loop unrolled by 4
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            nbD2[q * 64 + lane] = d2q[q];
+            nbS[q * 64 + lane] = sq[q];
+            nbI[q * 64 + lane] = (unsigned short)jq[q];
+        }
+        __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
+        __builtin_amdgcn_wave_barrier();
+        __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
+        for (int qi = 0; qi < a.kact - 1; ++qi) {
+            const float d2i = nbD2[qi * 64 + lane], si = nbS[qi * 64 + lane];
+            const int ui = nbI[qi * 64 + lane];
+            const float2 li = reinterpret_cast<const float2 *>(a.l2d)[ui];
+            const float lxi = li.x - ox, lyi = li.y - oy;
+            const float *invrow = a.inv2 + (size_t)ui * a.g;
+            for (int qb = qi + 1; qb < a.kact; qb += 4) {
+                float inv[4], d2j[4], sj[4], lxj[4], lyj[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const int qj = qb + u;
+                    const bool ok = qj < a.kact;
+                    const int vj = ok ? nbI[qj * 64 + lane] : 0;
+                    inv[u] = ok ? invrow[vj] : -1.f;
+                    d2j[u] = ok ? nbD2[qj * 64 + lane] : 0.f;
+                    sj[u] = ok ? nbS[qj * 64 + lane] : 0.f;
+                    const float2 lv = reinterpret_cast<const float2 *>(a.l2d)[vj];
+                    lxj[u] = lv.x - ox;
+                    lyj[u] = lv.y - oy;
+                }
+#pragma unroll
+                for (int u = 0; u < 4; ++u)
+                    pair_term(d2i, si, lxi, lyi, d2j[u], sj[u], lxj[u], lyj[u], inv[u]);
+            }
+        }
+        __builtin_amdgcn_wave_barrier();
+    }
+    // 2x2 solve in FP64 (Cramer's rule)
+    const double m00 = M00, m01 = M01, m11 = M11, rr0 = r0, rr1 = r1;
+    const double det = m00 * m11 - m01 * m01;
+    const double tr = m00 + m11;
+    if (ill || !(det > 0.0) || 0.25 * tr * tr > ILL_COND * det) reason |= R_ILLCOND;
+    if (valid && reason == 0) {
+        const double px = (rr0 * m11 - m01 * rr1) / det;
+        const double py = (m00 * rr1 - m01 * rr0) / det;
+        reinterpret_cast<float2 *>(a.out)[pi] = make_float2((float)((double)ox + px),
+                                                            (float)((double)oy + py));
+    }
+    return reason;
+}
+
+// Projection only (phases of scores, pairs and solve) from given k nearest
+// landmarks (knn_idx / knn_d2, sorted by (distance, index)), e.g. cached from
+// an earlier call with the same high-dimensional landmarks.
+template <int KP>
+__global__ void __launch_bounds__(256) embed_project(EmbedArgs a) {
+    extern __shared__ __align__(16) unsigned char smem[];
+    const int lane = threadIdx.x & 63;
+    const int wave = threadIdx.x >> 6;
+    const int wpb = blockDim.x >> 6;
+    unsigned char *wsm = smem + (size_t)wave * (KP * 64 * 10);
+    float *nbD2 = reinterpret_cast<float *>(wsm);
+    float *nbS = nbD2 + KP * 64;
+    unsigned short *nbI = reinterpret_cast<unsigned short *>(nbS + KP * 64);
+    const int64_t nwt = (a.n + 63) / 64;
+    for (int64_t wt = (int64_t)blockIdx.x * wpb + wave; wt < nwt; wt += (int64_t)gridDim.x * wpb) {
+        const int64_t pi = wt * 64 + lane;
+        const bool valid = pi < a.n;
+        double sk[KP];
+#pragma unroll
+        for (int q = 0; q < KP; ++q) {
+            sk[q] = INFINITY;
+            if (valid && q < a.k)
+                sk[q] = pack_key(a.knn_d2[pi * a.k + q], a.knn_idx[pi * a.k + q]);
+        }
+        const unsigned reason = project_point<KP>(a, sk, lane, valid, pi, 0u, nbD2, nbS, nbI);
+        if (valid && reason) {
+            const unsigned long long slot = atomicAdd(&a.counters[C_FB_LEN], 1ull);
+            a.fb_list[slot] = (int32_t)pi;
+            a.fb_reason[slot] = (uint8_t)reason;
+        }
+    }
+}
+
 template <int MODE, int DC, int KP>
 __global__ void __launch_bounds__(512) embed_main(EmbedArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
@@ -350,7 +536,7 @@ __global__ void __launch_bounds__(512) embed_main(EmbedArgs a) {
         __builtin_amdgcn_wave_barrier();
 
         // k-th and (k+1)-th rescored distances
-        float d2k = 0.f, d2k1 = INFINITY, d2first = key_d2(sk[0]);
+        float d2k = 0.f, d2k1 = INFINITY;
 #pragma unroll
         for (int q = 0; q < KP; ++q) {
             if (q == a.k - 1) d2k = key_d2(sk[q]);
@@ -382,98 +568,8 @@ __global__ void __launch_bounds__(512) embed_main(EmbedArgs a) {
         }
 
         if (!a.knn_only) {
-            // ---------------- phase C: scores
-            float dl[KP];
-            float mu = 0.f;
-#pragma unroll
-            for (int q = 0; q < KP; ++q) {
-                dl[q] = (q < a.k) ? sqrtf(key_d2(sk[q])) : 0.f;
-                if (q < a.k) mu = fmaf(dl[q], 1.f / (float)(q + 1), mu);
-            }
-            mu /= a.Wk;
-            float var = 0.f;
-#pragma unroll
-            for (int q = 0; q < KP; ++q) {
-                if (q < a.k) {
-                    const float e = dl[q] - mu;
-                    var = fmaf(e * e, 1.f / (float)(q + 1), var);
-                }
-            }
-            var /= a.Wk;
-            const float dk = sqrtf(d2k);
-            const bool flat = !(var > 1e-30f * mu * mu);
-            const float isig = flat ? 0.f : a.boost * rsqrtf(var);
-            if (d2first == d2k) reason |= R_DEGEN;
-            const int lu0 = key_idx(sk[0]);
-            const float ox = a.l2d[2 * lu0], oy = a.l2d[2 * lu0 + 1];
-            float ssum = 0.f;
-            float M00 = 0.f, M01 = 0.f, M11 = 0.f, r0 = 0.f, r1 = 0.f;
-#pragma unroll
-            for (int q = 0; q < KP; ++q) {
-                if (q < a.k) {
-                    const float e = flat ? 1.f : __expf((mu - dl[q]) * isig);
-                    const float c = a.use_cutoff ? -expm1f(a.cutoff * (dl[q] - dk) / dk) : 1.f;
-                    const float s = (d2first == d2k) ? 0.f : e * c;
-                    const int j = key_idx(sk[q]);
-                    const float lx = a.l2d[2 * j] - ox, ly = a.l2d[2 * j + 1] - oy;
-                    ssum += s;
-                    const float gs = a.gravity * s;
-                    M00 += gs;
-                    M11 += gs;
-                    r0 = fmaf(gs, lx, r0);
-                    r1 = fmaf(gs, ly, r1);
-                    nbD2[q * 64 + lane] = key_d2(sk[q]);
-                    nbS[q * 64 + lane] = s;
-                    nbI[q * 64 + lane] = (unsigned short)j;
-                }
-            }
-            if (!(ssum > 0.f)) reason |= R_DEGEN;
-            __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
             __builtin_amdgcn_wave_barrier();
-            __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
-
-            // ---------------- pairs (i < j among the neighbours with non-zero score)
-            const bool unit_adjust = a.adjust == 1.0f;
-            bool ill = false;
-            for (int qi = 0; qi < a.kact; ++qi) {
-                const float d2i = nbD2[qi * 64 + lane], si = nbS[qi * 64 + lane];
-                const int ui = nbI[qi * 64 + lane];
-                const float lxi = a.l2d[2 * ui] - ox, lyi = a.l2d[2 * ui + 1] - oy;
-                const float *invrow = a.inv2 + (size_t)ui * a.g;
-                for (int qj = qi + 1; qj < a.kact; ++qj) {
-                    const float d2j = nbD2[qj * 64 + lane], sj = nbS[qj * 64 + lane];
-                    const int vj = nbI[qj * 64 + lane];
-                    const float2 lv = reinterpret_cast<const float2 *>(a.l2d)[vj];
-                    const float hx = (lv.x - ox) - lxi, hy = (lv.y - oy) - lyi;
-                    const float inv = invrow[vj];
-                    const float hh = fmaf(hx, hx, hy * hy);
-                    if (inv < 0.f || hh == 0.f) continue;
-                    if (fmaxf(d2i, d2j) * inv > ILL_PAIR) ill = true;
-                    const float D = fmaf(d2i - d2j, inv, 0.5f);
-                    const float ihh = 1.f / hh;
-                    const float q = si * sj * (unit_adjust ? ihh : exp2f(-a.adjust * __log2f(hh)));
-                    const float qh = q * ihh;
-                    const float t = fmaf(D, hh, fmaf(hx, lxi, hy * lyi));
-                    const float qhx = qh * hx, qhy = qh * hy;
-                    M00 = fmaf(qhx, hx, M00);
-                    M01 = fmaf(qhx, hy, M01);
-                    M11 = fmaf(qhy, hy, M11);
-                    r0 = fmaf(qhx, t, r0);
-                    r1 = fmaf(qhy, t, r1);
-                }
-            }
-            // ---------------- 2x2 solve in FP64 (Cramer's rule)
-            const double m00 = M00, m01 = M01, m11 = M11, rr0 = r0, rr1 = r1;
-            const double det = m00 * m11 - m01 * m01;
-            const double tr = m00 + m11;
-            if (ill || !(det > 0.0) || 0.25 * tr * tr > ILL_COND * det) reason |= R_ILLCOND;
-            if (valid && reason == 0) {
-                const double px = (rr0 * m11 - m01 * rr1) / det;
-                const double py = (m00 * rr1 - m01 * rr0) / det;
-                a.out[2 * pi] = (float)((double)ox + px);
-                a.out[2 * pi + 1] = (float)((double)oy + py);
-            }
-            __builtin_amdgcn_wave_barrier();
+            reason = project_point<KP>(a, sk, lane, valid, pi, reason, nbD2, nbS, nbI);
         }
         if (valid && reason) {
             const unsigned long long slot = atomicAdd(&a.counters[C_FB_LEN], 1ull);

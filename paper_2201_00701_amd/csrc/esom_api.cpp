@@ -164,10 +164,16 @@ Plan make_plan(int d, int g, int k, int mode, int candidates) {
     return p;
 }
 
-// Enqueues preparation + fast kernel + exact path.  knn_only: k-nearest only.
+}  // namespace
+
+namespace esom {
+// Enqueues preparation + fast kernel + exact path.  what: EMBED_FULL,
+// EMBED_KNN_ONLY (k nearest only) or EMBED_PROJECT (scores/pairs/solve from
+// the given knn_idx / knn_d2).
 int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const float *L,
               const float *l2d, int g, const esom_params &P, float *out, int32_t *knn_idx,
-              float *knn_d2, int knn_only, hipStream_t s) {
+              float *knn_d2, int what, hipStream_t s) {
+    const int knn_only = what == EMBED_KNN_ONLY;
     const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
     int st = ensure_scratch(c, n, g, pl.dp, s);
     if (st != ESOM_OK) return st;
@@ -225,7 +231,13 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
     a.fb_reason = c->sc.fb_reason;
     a.counters = c->counters;
     a.knn_only = knn_only;
-    if (pl.fast) {
+    if (what == EMBED_PROJECT && pl.kp != 0) {
+        e = launch_project(a, pl.kp, c->num_cus, s);
+        if (e != hipSuccess) return hip_fail(e, "projection kernel launch");
+        if (timed) (void)hipEventRecord(ev[2], s);
+        e = launch_fallback(a, c->num_cus, s);
+        if (e != hipSuccess) return hip_fail(e, "exact-path launch");
+    } else if (pl.fast) {
         e = launch_embed(a, P.mode, pl.kp, c->num_cus, c->lds_per_block, s);
         if (e != hipSuccess) return hip_fail(e, "embed kernel launch");
         if (timed) (void)hipEventRecord(ev[2], s);
@@ -243,7 +255,22 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
     return ESOM_OK;
 }
 
-}  // namespace
+size_t ctx_held_bytes(const esom_ctx *c) { return c->held; }
+
+void ctx_trim(esom_ctx *c) {
+    dev_free(c, c->arena, c->arena_bytes);
+    c->arena_bytes = 0;
+    c->cap_n = c->cap_g = c->cap_dp = 0;
+}
+
+size_t embed_scratch_bytes(int64_t n, int g, int d) {
+    Scratch sc;
+    return carve(sc, nullptr, n, g, 16 * ((d + 15) / 16));
+}
+
+int fail_msg(int code, const char *msg) { return fail(code, "%s", msg); }
+
+}  // namespace esom
 
 extern "C" {
 
@@ -350,7 +377,7 @@ int esom_embed(esom_ctx *c, const float *X, int64_t n, int32_t d, int64_t ldx, c
     if (n == 0) return ESOM_OK;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
-    return run_embed(c, X, n, d, ldx, L_hd, L_2d, g, P, out, knn_idx, knn_dist2, 0,
+    return run_embed(c, X, n, d, ldx, L_hd, L_2d, g, P, out, knn_idx, knn_dist2, EMBED_FULL,
                      static_cast<hipStream_t>(stream));
 }
 
@@ -390,7 +417,7 @@ int esom_landmark_update(esom_ctx *c, const float *X, int64_t n, int32_t d, int6
         esom_default_params(&P);
         P.k = 1;
         P.mode = ESOM_MODE_FP32;
-        st = run_embed(c, X, n, d, ldx, L_hd, L_2d, g, P, nullptr, c->nearest, nullptr, 1, s);
+        st = run_embed(c, X, n, d, ldx, L_hd, L_2d, g, P, nullptr, c->nearest, nullptr, EMBED_KNN_ONLY, s);
         if (st != ESOM_OK) return st;
         near = c->nearest;
     }

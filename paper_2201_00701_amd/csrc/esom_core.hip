@@ -312,6 +312,23 @@ hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, hipStream_t s
     return hipGetLastError();
 }
 
+// ---------------------------------------------------------------- projection from given neighbours
+
+hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s) {
+    const int block = 256, wpb = 4;
+    const size_t smem = (size_t)wpb * kp * 64 * 10;
+    long long blocks = ((a.n + 63) / 64 + wpb - 1) / wpb;
+    if (blocks > (long long)num_cus * 8) blocks = (long long)num_cus * 8;
+    if (blocks < 1) blocks = 1;
+    if (kp == 8)
+        hipLaunchKernelGGL(embed_project<8>, dim3((unsigned)blocks), dim3(block), smem, s, a);
+    else if (kp == 16)
+        hipLaunchKernelGGL(embed_project<16>, dim3((unsigned)blocks), dim3(block), smem, s, a);
+    else
+        hipLaunchKernelGGL(embed_project<32>, dim3((unsigned)blocks), dim3(block), smem, s, a);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- main kernel dispatch
 
 // Instantiation units (embed_inst.hip, one object per (mode, KP)); each

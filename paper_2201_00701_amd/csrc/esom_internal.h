@@ -83,6 +83,7 @@ hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long lo
 hipError_t launch_embed(const EmbedArgs &a, int mode, int kp, int num_cus, size_t lds_per_block,
                         hipStream_t s);
 hipError_t launch_fallback(const EmbedArgs &a, int num_cus, hipStream_t s);
+hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s);
 hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, hipStream_t s);
 
 // Landmark update (esom_update.hip).
@@ -98,5 +99,15 @@ struct UpdateArgs {
 };
 size_t update_workspace_bytes(int64_t n, int g, int d);
 hipError_t launch_update(const UpdateArgs &u, void *ws, int num_cus, hipStream_t s);
+
+// Context-level helpers shared with the serving runtime (esom_api.cpp).
+enum EmbedWhat { EMBED_FULL = 0, EMBED_KNN_ONLY = 1, EMBED_PROJECT = 2 };
+int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const float *L,
+              const float *l2d, int g, const esom_params &P, float *out, int32_t *knn_idx,
+              float *knn_d2, int what, hipStream_t s);
+size_t ctx_held_bytes(const esom_ctx *c);
+void ctx_trim(esom_ctx *c);
+size_t embed_scratch_bytes(int64_t n, int g, int d);
+int fail_msg(int code, const char *msg);
 
 }  // namespace esom

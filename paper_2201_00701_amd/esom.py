@@ -46,6 +46,26 @@ class esom_stats(ctypes.Structure):
                 for n, t in self._fields_}
 
 
+class esom_request_info(ctypes.Structure):
+    _fields_ = [("submit_ms", ctypes.c_double), ("start_ms", ctypes.c_double),
+                ("done_ms", ctypes.c_double), ("n", ctypes.c_int64), ("cache_hit", ctypes.c_int32),
+                ("graph_replay", ctypes.c_int32), ("status", ctypes.c_int32),
+                ("reserved", ctypes.c_int32)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_ if n != "reserved"}
+
+
+class esom_serve_stats(ctypes.Structure):
+    _fields_ = [(n, ctypes.c_int64) for n in (
+        "completed", "failed", "rejected", "points", "cache_hits", "graph_replays", "queued",
+        "in_flight", "slots", "budget_bytes", "resident_bytes", "held_bytes", "peak_bytes")] + [
+        ("now_ms", ctypes.c_double)]
+
+    def as_dict(self):
+        return {n: getattr(self, n) for n, _ in self._fields_}
+
+
 class EsomError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("esom error %d: %s" % (code, msg))
@@ -86,6 +106,22 @@ def load(path: str = LIB_PATH):
     lib.esom_get_stats.restype = ctypes.c_int
     lib.esom_set_timing.argtypes = [_vp, _i32]
     lib.esom_set_timing.restype = ctypes.c_int
+    u64p = ctypes.POINTER(ctypes.c_uint64)
+    lib.esom_serve_create.argtypes = [ctypes.c_int, _sz, _i32, ctypes.POINTER(_vp)]
+    lib.esom_serve_create.restype = ctypes.c_int
+    lib.esom_serve_destroy.argtypes = [_vp]
+    lib.esom_serve_destroy.restype = None
+    lib.esom_serve_dataset_put.argtypes = [_vp, _vp, _i64, _i32, u64p]
+    lib.esom_serve_dataset_put.restype = ctypes.c_int
+    lib.esom_serve_dataset_drop.argtypes = [_vp, ctypes.c_uint64]
+    lib.esom_serve_dataset_drop.restype = ctypes.c_int
+    lib.esom_serve_submit.argtypes = [_vp, ctypes.c_uint64, _vp, _i64, _i32, _vp, _vp, _i32,
+                                      ctypes.POINTER(esom_params), _vp, u64p]
+    lib.esom_serve_submit.restype = ctypes.c_int
+    lib.esom_serve_wait.argtypes = [_vp, ctypes.c_uint64, _i32, ctypes.POINTER(esom_request_info)]
+    lib.esom_serve_wait.restype = ctypes.c_int
+    lib.esom_serve_get_stats.argtypes = [_vp, ctypes.POINTER(esom_serve_stats)]
+    lib.esom_serve_get_stats.restype = ctypes.c_int
     _lib = lib
     return lib
 
@@ -243,3 +279,112 @@ class Context:
 
     def stats(self, reset=False, stream=None):
         return esom_get_stats(self.handle, self._stream(stream), reset)
+
+
+# ---- serving (host arrays) ----------------------------------------------------------
+
+def esom_serve_create(device=0, hbm_budget_bytes=0, n_slots=4) -> int:
+    h = _vp()
+    _check(load().esom_serve_create(device, hbm_budget_bytes, n_slots, ctypes.byref(h)))
+    return h.value
+
+
+def esom_serve_destroy(srv) -> None:
+    load().esom_serve_destroy(srv)
+
+
+def esom_serve_dataset_put(srv, X_ptr, n, d) -> int:
+    did = ctypes.c_uint64()
+    _check(load().esom_serve_dataset_put(srv, X_ptr, n, d, ctypes.byref(did)))
+    return did.value
+
+
+def esom_serve_dataset_drop(srv, dataset_id) -> int:
+    return load().esom_serve_dataset_drop(srv, dataset_id)
+
+
+def esom_serve_submit(srv, dataset_id, X_ptr, n, d, L_ptr, l_ptr, g, params, out_ptr):
+    rid = ctypes.c_uint64()
+    rc = load().esom_serve_submit(srv, dataset_id, X_ptr or None, n, d, L_ptr, l_ptr, g,
+                                  ctypes.byref(params), out_ptr, ctypes.byref(rid))
+    return rc, rid.value
+
+
+def esom_serve_wait(srv, request_id, timeout_ms=-1):
+    info = esom_request_info()
+    rc = load().esom_serve_wait(srv, request_id, timeout_ms, ctypes.byref(info))
+    return rc, info.as_dict()
+
+
+def esom_serve_get_stats(srv) -> dict:
+    st = esom_serve_stats()
+    _check(load().esom_serve_get_stats(srv, ctypes.byref(st)))
+    return st.as_dict()
+
+
+class Server:
+    """Serving runtime on host numpy arrays (float32, C-contiguous)."""
+
+    def __init__(self, device=0, hbm_budget_bytes=0, n_slots=4):
+        self.handle = esom_serve_create(device, hbm_budget_bytes, n_slots)
+        self._keep = {}
+
+    def close(self):
+        if self.handle:
+            esom_serve_destroy(self.handle)
+            self.handle = None
+
+    def __del__(self):
+        try:
+            self.close()
+        except Exception:
+            pass
+
+    @staticmethod
+    def _f32(a, name):
+        import numpy as np
+        a = np.asarray(a)
+        if a.dtype != np.float32 or not a.flags.c_contiguous or a.ndim != 2:
+            raise TypeError("%s must be a C-contiguous 2-D float32 array" % name)
+        return a
+
+    def put(self, X):
+        X = self._f32(X, "X")
+        return esom_serve_dataset_put(self.handle, X.ctypes.data, X.shape[0], X.shape[1])
+
+    def drop(self, dataset_id):
+        _check(esom_serve_dataset_drop(self.handle, dataset_id))
+
+    def submit(self, L, l, k=16, mode="fp32", dataset=0, X=None, out=None, **params):
+        import numpy as np
+        L = self._f32(L, "L")
+        l = self._f32(l, "l")
+        if dataset:
+            n = None
+        else:
+            X = self._f32(X, "X")
+            n = X.shape[0]
+        p = esom_default_params(k=k, mode=mode, **params)
+        if out is None:
+            if n is None:
+                raise ValueError("pass out= (n x 2 float32) for a resident dataset")
+            out = np.empty((n, 2), np.float32)
+        out = self._f32(out, "out")
+        rc, rid = esom_serve_submit(self.handle, dataset, 0 if dataset else X.ctypes.data,
+                                    0 if dataset else X.shape[0], L.shape[1], L.ctypes.data,
+                                    l.ctypes.data, L.shape[0], p, out.ctypes.data)
+        _check(rc)
+        self._keep[rid] = (X, out, L, l)
+        return rid
+
+    def wait(self, rid, timeout_ms=-1):
+        rc, info = esom_serve_wait(self.handle, rid, timeout_ms)
+        if rc == ESOM_ETIMEOUT:
+            return None
+        keep = self._keep.pop(rid, None)
+        _check(rc)
+        info["out"] = keep[1]
+        return info
+
+    def stats(self):
+        return esom_serve_get_stats(self.handle)

@@ -22,7 +22,9 @@ def test_header_declares_the_entry_points():
     names = esom.header_functions()
     for required in ("esom_create", "esom_destroy", "esom_last_error", "esom_embed",
                      "esom_landmark_update", "esom_sync", "esom_get_stats",
-                     "esom_default_params", "esom_set_timing"):
+                     "esom_default_params", "esom_set_timing", "esom_serve_create",
+                     "esom_serve_destroy", "esom_serve_dataset_put", "esom_serve_dataset_drop",
+                     "esom_serve_submit", "esom_serve_wait", "esom_serve_get_stats"):
         assert required in names
 
 
@@ -43,6 +45,8 @@ def test_param_struct_matches_header_defaults():
     assert abs(p.gravity - 1e-5) < 1e-12
     assert ctypes.sizeof(esom.esom_params) == 28
     assert ctypes.sizeof(esom.esom_stats) == 96
+    assert ctypes.sizeof(esom.esom_request_info) == 48
+    assert ctypes.sizeof(esom.esom_serve_stats) == 112
 
 
 def test_binding_never_imports_the_oracle():

@@ -327,7 +327,8 @@ __global__ void __launch_bounds__(256) embed_project(EmbedArgs a) {
             if (valid && q < a.k)
                 sk[q] = pack_key(a.knn_d2[pi * a.k + q], a.knn_idx[pi * a.k + q]);
         }
-        const unsigned reason = project_point<KP>(a, sk, lane, valid, pi, 0u, nbD2, nbS, nbI);
+        unsigned reason = (valid && a.knn_mark && a.knn_mark[pi]) ? (unsigned)R_NEARTIE : 0u;
+        reason = project_point<KP>(a, sk, lane, valid, pi, reason, nbD2, nbS, nbI);
         if (valid && reason) {
             const unsigned long long slot = atomicAdd(&a.counters[C_FB_LEN], 1ull);
             a.fb_list[slot] = (int32_t)pi;
@@ -556,7 +557,8 @@ __global__ void __launch_bounds__(512) embed_main(EmbedArgs a) {
             if (m > a.k && d2k1 - d2k <= 4.f * (DP + 3) * U32 * d2k1) reason |= R_NEARTIE;
         }
 
-        // knn outputs (overwritten by the exact path for listed points)
+        // knn outputs (the exact path rewrites those of uncertified / near-tie points)
+        if (valid && a.knn_mark) a.knn_mark[pi] = (reason & (R_UNCERT | R_NEARTIE)) ? 1 : 0;
         if (valid && (a.knn_idx || a.knn_d2)) {
 #pragma unroll
             for (int q = 0; q < KP; ++q) {

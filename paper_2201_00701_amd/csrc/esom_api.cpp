@@ -172,7 +172,7 @@ namespace esom {
 // the given knn_idx / knn_d2).
 int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const float *L,
               const float *l2d, int g, const esom_params &P, float *out, int32_t *knn_idx,
-              float *knn_d2, int what, hipStream_t s) {
+              float *knn_d2, int what, hipStream_t s, uint8_t *knn_mark) {
     const int knn_only = what == EMBED_KNN_ONLY;
     const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
     int st = ensure_scratch(c, n, g, pl.dp, s);
@@ -231,6 +231,7 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
     a.fb_reason = c->sc.fb_reason;
     a.counters = c->counters;
     a.knn_only = knn_only;
+    a.knn_mark = knn_mark;
     if (what == EMBED_PROJECT && pl.kp != 0) {
         e = launch_project(a, pl.kp, c->num_cus, s);
         if (e != hipSuccess) return hip_fail(e, "projection kernel launch");

@@ -182,10 +182,14 @@ __global__ void __launch_bounds__(64) embed_exact(EmbedArgs a, int all_points) {
             }
             __syncthreads();
         }
-        if (lane < k) {
+        // Neighbours of points listed only for the projection (ill-conditioned,
+        // degenerate) were already certified by the fast kernel: keep its outputs.
+        const bool hd_reason = all_points || (reason & (R_UNCERT | R_NEARTIE)) || a.knn_only;
+        if (lane < k && hd_reason) {
             if (a.knn_idx) a.knn_idx[pi * k + lane] = bad ? -1 : sel_j[lane];
             if (a.knn_d2) a.knn_d2[pi * k + lane] = (float)sel_d[lane];
         }
+        if (lane == 0 && a.knn_mark && hd_reason) a.knn_mark[pi] = 1;
         if (a.knn_only) continue;
         if (bad) {
             if (lane == 0) {

@@ -75,6 +75,11 @@ struct EmbedArgs {
     unsigned long long *counters;
     int knn_only;  // 1: only write knn outputs (no projection)
     int lds_rows;  // 1: the block stages Lpad in LDS (row stride dp + 4 floats)
+    // Optional per-point mark beside knn outputs (serving cache): 1 when the
+    // point's neighbours came from the exact path because of the screen
+    // (uncertified or near tie); a projection from cached neighbours sends
+    // such points to the exact path again.
+    uint8_t *knn_mark;
 };
 
 // Launchers (esom_embed.hip).
@@ -104,7 +109,7 @@ hipError_t launch_update(const UpdateArgs &u, void *ws, int num_cus, hipStream_t
 enum EmbedWhat { EMBED_FULL = 0, EMBED_KNN_ONLY = 1, EMBED_PROJECT = 2 };
 int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const float *L,
               const float *l2d, int g, const esom_params &P, float *out, int32_t *knn_idx,
-              float *knn_d2, int what, hipStream_t s);
+              float *knn_d2, int what, hipStream_t s, uint8_t *knn_mark = nullptr);
 size_t ctx_held_bytes(const esom_ctx *c);
 void ctx_trim(esom_ctx *c);
 size_t embed_scratch_bytes(int64_t n, int g, int d);

@@ -60,6 +60,7 @@ struct Dataset {
     // k-nearest cache
     int32_t *kidx = nullptr;
     float *kd2 = nullptr;
+    uint8_t *kmark = nullptr;
     size_t cache_bytes = 0;
     bool cache_valid = false;
     bool cache_busy = false;
@@ -111,8 +112,13 @@ struct esom_server {
     size_t budget = 0;
     size_t resident = 0;  // datasets + caches
     std::chrono::steady_clock::time_point t0;
-    std::mutex mu;
-    std::condition_variable cv_sched, cv_done;
+    std::mutex mu;                 // all state below; may be held across HIP calls
+    std::condition_variable cv_done;
+    // Wake-ups for the scheduler.  note_mu is never held across a HIP call, so
+    // the stream host functions that take it can never block device progress.
+    std::mutex note_mu;
+    std::condition_variable cv_note;
+    bool note_pending = false;
     std::deque<Request *> queue;
     std::map<uint64_t, std::unique_ptr<Request>> requests;
     std::map<uint64_t, std::unique_ptr<Dataset>> datasets;
@@ -192,14 +198,19 @@ void slot_free_buffers(Slot &sl) {
     ctx_trim(sl.ctx);
 }
 
-void host_done(void *arg) {
-    // Runs on a HIP runtime thread: no HIP calls here.
-    auto *pair = static_cast<std::pair<esom_server *, Slot *> *>(arg);
+void wake(esom_server *S) {
     {
-        std::lock_guard<std::mutex> lk(pair->first->mu);
-        pair->second->finished.store(true);
+        std::lock_guard<std::mutex> lk(S->note_mu);
+        S->note_pending = true;
     }
-    pair->first->cv_sched.notify_all();
+    S->cv_note.notify_all();
+}
+
+void host_done(void *arg) {
+    // Runs on a HIP runtime thread: no HIP calls and not the state mutex here.
+    auto *pair = static_cast<std::pair<esom_server *, Slot *> *>(arg);
+    pair->second->finished.store(true);
+    wake(pair->first);
     delete pair;
 }
 
@@ -231,6 +242,7 @@ int launch_request(esom_server *S, Slot &sl, Request &r) {
     int what = EMBED_FULL;
     int32_t *kidx = nullptr;
     float *kd2 = nullptr;
+    uint8_t *kmark = nullptr;
     sl.cache_writer = false;
     if (ds && !ds->cache_busy && r.P.k <= 32) {
         if (ds->cache_valid && ds->cache_key == r.hd_key) {
@@ -238,20 +250,23 @@ int launch_request(esom_server *S, Slot &sl, Request &r) {
             r.cache_hit = true;
         } else {
             const size_t need = (size_t)ds->n * r.P.k;
-            const size_t bytes = need * (sizeof(int32_t) + sizeof(float));
+            const size_t bytes = need * (sizeof(int32_t) + sizeof(float)) + (size_t)ds->n;
             if (bytes > ds->cache_bytes) {
                 const size_t have = S->resident + slot_held(S) - ds->cache_bytes;
                 if (have + bytes <= S->budget || S->budget == 0) {
                     if (ds->kidx) (void)hipFree(ds->kidx);
                     if (ds->kd2) (void)hipFree(ds->kd2);
+                    if (ds->kmark) (void)hipFree(ds->kmark);
                     S->resident -= ds->cache_bytes;
                     ds->kidx = nullptr;
                     ds->kd2 = nullptr;
+                    ds->kmark = nullptr;
                     ds->cache_bytes = 0;
                     if (hipMalloc(reinterpret_cast<void **>(&ds->kidx), need * sizeof(int32_t)) ==
                             hipSuccess &&
                         hipMalloc(reinterpret_cast<void **>(&ds->kd2), need * sizeof(float)) ==
-                            hipSuccess) {
+                            hipSuccess &&
+                        hipMalloc(reinterpret_cast<void **>(&ds->kmark), (size_t)ds->n) == hipSuccess) {
                         ds->cache_bytes = bytes;
                         S->resident += bytes;
                     }
@@ -266,6 +281,7 @@ int launch_request(esom_server *S, Slot &sl, Request &r) {
             ds->cache_busy = true;
             kidx = ds->kidx;
             kd2 = ds->kd2;
+            kmark = ds->kmark;
         }
     }
 
@@ -285,7 +301,8 @@ int launch_request(esom_server *S, Slot &sl, Request &r) {
         if (!ds && hipMemcpyAsync(sl.dX, r.Xh, (size_t)r.n * r.d * sizeof(float),
                                   hipMemcpyHostToDevice, s) != hipSuccess)
             return fail_msg(ESOM_EDEVICE, "serving: point upload failed");
-        int e = run_embed(sl.ctx, X, r.n, r.d, r.d, sl.dL, sl.dl, r.g, r.P, sl.dout, kidx, kd2, what, s);
+        int e = run_embed(sl.ctx, X, r.n, r.d, r.d, sl.dL, sl.dl, r.g, r.P, sl.dout, kidx, kd2, what, s,
+                          kmark);
         if (e != ESOM_OK) return e;
         if (hipMemcpyAsync(sl.hout, sl.dout, nout * sizeof(float), hipMemcpyDeviceToHost, s) != hipSuccess)
             return fail_msg(ESOM_EDEVICE, "serving: result download failed");
@@ -346,6 +363,7 @@ void finish_request(esom_server *S, Slot &sl) {
                 (void)hipFree(ds.X);
                 if (ds.kidx) (void)hipFree(ds.kidx);
                 if (ds.kd2) (void)hipFree(ds.kd2);
+                if (ds.kmark) (void)hipFree(ds.kmark);
                 S->resident -= ds.bytes + ds.cache_bytes;
                 S->datasets.erase(it);
             }
@@ -363,8 +381,8 @@ void finish_request(esom_server *S, Slot &sl) {
 
 void scheduler(esom_server *S) {
     (void)hipSetDevice(S->device);
-    std::unique_lock<std::mutex> lk(S->mu);
     for (;;) {
+        std::unique_lock<std::mutex> lk(S->mu);
         bool progressed = false;
         for (auto &sl : S->slots) {
             if (sl->cur && sl->finished.load()) {
@@ -422,7 +440,10 @@ void scheduler(esom_server *S) {
         bool inflight = false;
         for (auto &sl : S->slots) inflight |= sl->cur != nullptr;
         if (S->stop && S->queue.empty() && !inflight) break;
-        S->cv_sched.wait_for(lk, std::chrono::milliseconds(inflight ? 2 : 50));
+        lk.unlock();
+        std::unique_lock<std::mutex> nl(S->note_mu);
+        S->cv_note.wait_for(nl, std::chrono::milliseconds(50), [&] { return S->note_pending; });
+        S->note_pending = false;
     }
 }
 
@@ -469,7 +490,7 @@ void esom_serve_destroy(esom_server *S) {
         std::lock_guard<std::mutex> lk(S->mu);
         S->stop = true;
     }
-    S->cv_sched.notify_all();
+    wake(S);
     if (S->sched.joinable()) S->sched.join();
     (void)hipSetDevice(S->device);
     for (auto &sl : S->slots) {
@@ -486,6 +507,7 @@ void esom_serve_destroy(esom_server *S) {
         if (ds.X) (void)hipFree(ds.X);
         if (ds.kidx) (void)hipFree(ds.kidx);
         if (ds.kd2) (void)hipFree(ds.kd2);
+        if (ds.kmark) (void)hipFree(ds.kmark);
     }
     delete S;
 }
@@ -529,6 +551,7 @@ int esom_serve_dataset_drop(esom_server *S, uint64_t dataset_id) {
         (void)hipFree(ds.X);
         if (ds.kidx) (void)hipFree(ds.kidx);
         if (ds.kd2) (void)hipFree(ds.kd2);
+        if (ds.kmark) (void)hipFree(ds.kmark);
         S->resident -= ds.bytes + ds.cache_bytes;
         S->datasets.erase(it);
     }
@@ -586,7 +609,7 @@ int esom_serve_submit(esom_server *S, uint64_t dataset_id, const float *X_host, 
     S->queue.push_back(r.get());
     S->requests[r->id] = std::move(r);
     lk.unlock();
-    S->cv_sched.notify_all();
+    wake(S);
     return ESOM_OK;
 }
 

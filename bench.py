@@ -33,6 +33,33 @@ def alu_flops_per_point(g, d, k, cands):
     return g + 3.0 * cands * d + 30.0 * (k - 1) * (k - 2) / 2.0
 
 
+def kernel_sources_hash():
+    import hashlib
+    h = hashlib.sha256()
+    for f in ("embed_kernel.h", "embed_inst.hip", "esom_core.hip", "esom_internal.h"):
+        with open(os.path.join(ROOT, "paper_2201_00701_amd", "csrc", f), "rb") as fh:
+            h.update(fh.read())
+    return h.hexdigest()[:16]
+
+
+def measured_traffic(mode, workload):
+    """HBM bytes per launch of the fused kernel from the committed rocprofv3
+    FETCH_SIZE / WRITE_SIZE summary, or None when the kernel sources have
+    changed since those counters were taken (or for another workload)."""
+    if workload != "c2_fp32_1m":
+        return None
+    path = os.path.join(ROOT, "profiles", "embed_main_c2_1m_hbm_counters.txt")
+    try:
+        kv = dict(l.split(": ", 1) for l in open(path).read().splitlines()
+                  if ": " in l and not l.startswith("#"))
+    except OSError:
+        return None
+    if kv.get("kernel_sources_sha256_16") != kernel_sources_hash():
+        return None
+    v = kv.get("traffic_bytes_" + mode)
+    return float(v) if v is not None else None
+
+
 def cpu_baseline(w, seconds):
     import numpy as np
 
@@ -164,6 +191,9 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--calibrate-copy", action="store_true",
+                    help="also run a plain 256 MiB device copy (the reference kernel for "
+                         "scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
         print("bench.py measures one GPU: the projection is data-parallel over points and this "
@@ -216,16 +246,24 @@ def main():
             ach = 2.0 * n * g * d / (ms_main * 1e-3) / 1e12
             res["roofline"] = {"bound": "mfma", "achieved": ach, "peak": MFMA_FP32_PEAK_TFLOPS,
                                "unit": "TFLOP/s", "frac": ach / MFMA_FP32_PEAK_TFLOPS,
-                               "traffic": None}
+                               "traffic": measured_traffic(mode, args.workload)}
         else:
             ach = alu_flops_per_point(g, d, k, 2 * k) * n / (ms_main * 1e-3) / 1e12
             res["roofline"] = {"bound": "alu", "achieved": ach, "peak": VALU_FP32_PEAK_TFLOPS,
                                "unit": "TFLOP/s", "frac": ach / VALU_FP32_PEAK_TFLOPS,
-                               "traffic": None}
+                               "traffic": measured_traffic(mode, args.workload)}
         results[mode] = res
         print("bench: mode %s %.3f ms/step (main kernel %.3f ms) %.3g points/s"
               % (mode, ms_step, ms_main, res["value"]), file=sys.stderr, flush=True)
     ctx.close()
+
+    if args.calibrate_copy:
+        src = torch.empty(64 << 20, dtype=torch.float32, device="cuda").fill_(1.0)
+        dst = torch.empty_like(src)
+        for _ in range(3):
+            dst.copy_(src)
+        torch.cuda.synchronize()
+        del src, dst
 
     head = "bf16" if "bf16" in results else list(results)[0]
     line = {

@@ -36,6 +36,10 @@
 
 #include "esom_internal.h"
 
+#ifndef ESOM_TILE_PREFETCH
+#define ESOM_TILE_PREFETCH 0
+#endif
+
 namespace esom {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -46,6 +50,11 @@ constexpr float U32 = 5.9604645e-08f;     // 2^-24, FP32 unit roundoff
 constexpr float UBF16 = 0.00390625f;      // 2^-8, BF16 unit roundoff
 constexpr float ILL_PAIR = 64.0f;         // max(delta^2)/(2|L_u-L_v|^2) beyond this: exact path
 constexpr double ILL_COND = 64.0;         // (tr/2)^2/det beyond this: exact path
+
+// Largest block of the fused kernel: 12 waves (3 per SIMD, 168 registers per
+// lane) where the register budget of the instantiation allows it (BF16, padded
+// dimension <= 32), else 8 waves (256 registers).
+__host__ __device__ constexpr int main_max_block(int mode, int dc) { return (mode == 1 && dc <= 2) ? 768 : 512; }
 
 __device__ __forceinline__ unsigned bf16_bits_rne(float f) {
     unsigned u = __float_as_uint(f);
@@ -65,9 +74,10 @@ __device__ __forceinline__ int key_idx(double v) {
     return (int)((unsigned long long)__double_as_longlong(v) & 0x1FFFull);
 }
 
-// Ascending bitonic sort of N floats held in registers (N a power of two).
+// Ascending bitonic sort of N non-negative floats given as their bit
+// patterns (for those, integer order is float order; +inf sorts last).
 template <int N>
-__device__ __forceinline__ void sort_regs(float (&v)[N]) {
+__device__ __forceinline__ void sort_regs(int (&v)[N]) {
 #pragma unroll
     for (int k = 2; k <= N; k <<= 1) {
 #pragma unroll
@@ -76,32 +86,69 @@ __device__ __forceinline__ void sort_regs(float (&v)[N]) {
             for (int i = 0; i < N; ++i) {
                 const int l = i ^ j;
                 if (l > i) {
-                    const float a = v[i], b = v[l];
+                    const int a = v[i], b = v[l];
                     const bool up = (i & k) == 0;
-                    v[i] = up ? fminf(a, b) : fmaxf(a, b);
-                    v[l] = up ? fmaxf(a, b) : fminf(a, b);
+                    v[i] = up ? min(a, b) : max(a, b);
+                    v[l] = up ? max(a, b) : min(a, b);
                 }
             }
         }
     }
 }
 
+// FP64 minimum / maximum as single instructions.  fmin/fmax would add a
+// quieting step per operand for signalling NaNs, which never occur here (the
+// operands are packed keys built by integer operations, or +inf).
+__device__ __forceinline__ double vmin64(double a, double b) {
+    double r;
+    asm("v_min_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+__device__ __forceinline__ double vmax64(double a, double b) {
+    double r;
+    asm("v_max_f64 %0, %1, %2" : "=v"(r) : "v"(a), "v"(b));
+    return r;
+}
+
+// Insert v into the ascending list s; whatever falls off the end updates rej
+// (the smallest key ever rejected).
 template <int KP>
 __device__ __forceinline__ void insert_sorted(double (&s)[KP], double &rej, double v) {
 #pragma unroll
     for (int q = 0; q < KP; ++q) {
-        const double lo = fmin(s[q], v);
-        v = fmax(s[q], v);
+        const double lo = vmin64(s[q], v);
+        v = vmax64(s[q], v);
         s[q] = lo;
     }
-    rej = fmin(rej, v);
+    rej = vmin64(rej, v);
 }
 
-// Bytes of LDS one wave needs.
+// Next non-empty bitmap word of a lane: masks mk0 / mk1 of the words of the
+// two screen halves (bit tp = tile pair tp); row = the lane's words, stride 64
+// per tile pair, +32 for the second half.  nb = 0 when none is left.
+__device__ __forceinline__ void next_word(unsigned long long &mk0, unsigned long long &mk1,
+                                          const unsigned *row, unsigned &nb, int &nhh, int &ntp) {
+    nb = 0u;
+    if (mk0) {
+        nhh = 0;
+        ntp = __builtin_ctzll(mk0);
+        mk0 &= mk0 - 1ull;
+        nb = row[ntp * 64];
+    } else if (mk1) {
+        nhh = 1;
+        ntp = __builtin_ctzll(mk1);
+        mk1 &= mk1 - 1ull;
+        nb = row[ntp * 64 + 32];
+    }
+}
+
+// Bytes of LDS one wave needs: candidate bitmaps (2 W words per lane), or for
+// KP > 16 the neighbour staging of the pair loop in the same space; then
+// thresholds, norms and the per-lane masks of non-empty bitmap words.
 __host__ __device__ inline int wave_smem_bytes(int kp, int npair_tiles) {
     const int bits = 2 * npair_tiles * 64 * 4;
-    const int nbr = kp * 64 * 10;
-    return (bits > nbr ? bits : nbr) + 512;
+    const int nbr = kp > 16 ? kp * 64 * 10 : 0;
+    return (bits > nbr ? bits : nbr) + 512 + 1024;
 }
 
 template <int MODE, int DC>
@@ -116,36 +163,61 @@ struct PointOperand<0, DC> {  // FP32: lane holds dims 2s + h, s < 8 DC
     float b[2][8 * DC];
 };
 
+// One landmark tile's A operand and squared norms, as one lane holds them.
 template <int MODE, int DC>
-__device__ __forceinline__ void screen_tile(const EmbedArgs &a, const PointOperand<MODE, DC> &P,
-                                            int t, int lane, f32x16 (&acc)[2]) {
-    const int h = lane >> 5;
+struct TileRegs;
+template <int DC>
+struct TileRegs<1, DC> {
+    u32x4 a[DC];
+};
+template <int DC>
+struct TileRegs<0, DC> {
+    float a[8 * DC];
+};
+
+template <int MODE, int DC>
+__device__ __forceinline__ void load_tile(const EmbedArgs &a, int t, int lane, TileRegs<MODE, DC> &T) {
+    if constexpr (MODE == 1) {
+        const u32x4 *Ap = reinterpret_cast<const u32x4 *>(a.A) + (size_t)t * DC * 64 + lane;
+#pragma unroll
+        for (int c = 0; c < DC; ++c) T.a[c] = Ap[c * 64];
+    } else {
+        const float *Ap = reinterpret_cast<const float *>(a.A) + (size_t)t * (8 * DC) * 64 + lane;
+#pragma unroll
+        for (int s = 0; s < 8 * DC; ++s) T.a[s] = Ap[s * 64];
+    }
+}
+
+// Keys of tile t for both 32-point halves of the wave: acc[p] = |L|^2 + A B_p.
+template <int MODE, int DC>
+__device__ __forceinline__ void screen_tile(const EmbedArgs &a, int t, int lane, const TileRegs<MODE, DC> &T,
+                                            const PointOperand<MODE, DC> &P, f32x16 (&acc)[2]) {
     f32x16 nrm;
     {
-        const float4 *np = reinterpret_cast<const float4 *>(a.norms + (size_t)(t * 2 + h) * 16);
-        float4 n0 = np[0], n1 = np[1], n2 = np[2], n3 = np[3];
-        nrm[0] = n0.x; nrm[1] = n0.y; nrm[2] = n0.z; nrm[3] = n0.w;
-        nrm[4] = n1.x; nrm[5] = n1.y; nrm[6] = n1.z; nrm[7] = n1.w;
-        nrm[8] = n2.x; nrm[9] = n2.y; nrm[10] = n2.z; nrm[11] = n2.w;
-        nrm[12] = n3.x; nrm[13] = n3.y; nrm[14] = n3.z; nrm[15] = n3.w;
+        const float4 *np = reinterpret_cast<const float4 *>(a.norms + (size_t)(t * 2 + (lane >> 5)) * 16);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float4 n = np[i];
+            nrm[4 * i] = n.x;
+            nrm[4 * i + 1] = n.y;
+            nrm[4 * i + 2] = n.z;
+            nrm[4 * i + 3] = n.w;
+        }
     }
     acc[0] = nrm;
     acc[1] = nrm;
     if constexpr (MODE == 1) {
-        const u32x4 *Ap = reinterpret_cast<const u32x4 *>(a.A) + (size_t)t * DC * 64 + lane;
 #pragma unroll
         for (int c = 0; c < DC; ++c) {
-            const bf16x8 av = __builtin_bit_cast(bf16x8, Ap[c * 64]);
+            const bf16x8 av = __builtin_bit_cast(bf16x8, T.a[c]);
             acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, P.b[0][c], acc[0], 0, 0, 0);
             acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(av, P.b[1][c], acc[1], 0, 0, 0);
         }
     } else {
-        const float *Ap = reinterpret_cast<const float *>(a.A) + (size_t)t * (8 * DC) * 64 + lane;
 #pragma unroll
         for (int s = 0; s < 8 * DC; ++s) {
-            const float av = Ap[s * 64];
-            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, P.b[0][s], acc[0], 0, 0, 0);
-            acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(av, P.b[1][s], acc[1], 0, 0, 0);
+            acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(T.a[s], P.b[0][s], acc[0], 0, 0, 0);
+            acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(T.a[s], P.b[1][s], acc[1], 0, 0, 0);
         }
     }
 }
@@ -338,7 +410,7 @@ __global__ void __launch_bounds__(256) embed_project(EmbedArgs a) {
 }
 
 template <int MODE, int DC, int KP>
-__global__ void __launch_bounds__(512) embed_main(EmbedArgs a) {
+__global__ void __launch_bounds__(main_max_block(MODE, DC)) embed_main(EmbedArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int DP = 16 * DC;
     constexpr int RS = DP + 4;  // LDS row stride (floats): spreads rows over the banks
@@ -364,9 +436,11 @@ __global__ void __launch_bounds__(512) embed_main(EmbedArgs a) {
     float *nbD2 = reinterpret_cast<float *>(wsm);
     float *nbS = nbD2 + KP * 64;
     unsigned short *nbI = reinterpret_cast<unsigned short *>(nbS + KP * 64);
-    const int tail = (2 * W * 64 * 4 > KP * 64 * 10) ? 2 * W * 64 * 4 : KP * 64 * 10;
+    const int nbr_bytes = KP > 16 ? KP * 64 * 10 : 0;
+    const int tail = (2 * W * 64 * 4 > nbr_bytes) ? 2 * W * 64 * 4 : nbr_bytes;
     float *tauL = reinterpret_cast<float *>(wsm + tail);
     float *xnL = tauL + 64;
+    unsigned long long *maskL = reinterpret_cast<unsigned long long *>(xnL + 64);
 
     const float lmax = *a.lmax;
     const float us = (MODE == 1) ? UBF16 : U32;
@@ -413,58 +487,101 @@ __global__ void __launch_bounds__(512) embed_main(EmbedArgs a) {
             xnp[p] = part + __shfl_xor(part, 32);
         }
 
-        // ---------------- pass 1: group minima of the keys
-        float gmin[2][2][16];
+        // ---------------- pass 1: group minima of the approximate squared distances
+        // key + |x - c|^2 (bit patterns: integer minima, no NaN quieting).  The
+        // tiles are streamed with the next one's operands loaded ahead.
+        int gmin[2][2][16];
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) gmin[p][q][r] = INFINITY;
-        for (int tp = 0; tp < W; ++tp) {
+                for (int r = 0; r < 16; ++r) gmin[p][q][r] = 0x7F800000;
+        const int ntiles = 2 * W;
+        {
+            TileRegs<MODE, DC> cur, nxt;
+#if ESOM_TILE_PREFETCH
+            load_tile<MODE, DC>(a, 0, lane, cur);
+#endif
+            for (int tp = 0; tp < W; ++tp) {
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                f32x16 acc[2];
-                screen_tile<MODE, DC>(a, P, 2 * tp + half, lane, acc);
+                for (int half = 0; half < 2; ++half) {
+                    const int tn = 2 * tp + half + 1;
+#if ESOM_TILE_PREFETCH
+                    load_tile<MODE, DC>(a, tn < ntiles ? tn : ntiles - 1, lane, nxt);
+#else
+                    load_tile<MODE, DC>(a, tn - 1, lane, cur);
+#endif
+                    f32x16 acc[2];
+                    screen_tile<MODE, DC>(a, 2 * tp + half, lane, cur, P, acc);
 #pragma unroll
-                for (int p = 0; p < 2; ++p)
+                    for (int p = 0; p < 2; ++p)
 #pragma unroll
-                    for (int r = 0; r < 16; ++r) gmin[p][half][r] = fminf(gmin[p][half][r], acc[p][r]);
+                        for (int r = 0; r < 16; ++r)
+                            gmin[p][half][r] = min(gmin[p][half][r], __float_as_int(acc[p][r] + xnp[p]));
+#if ESOM_TILE_PREFETCH
+                    cur = nxt;
+#endif
+                }
             }
         }
-        // threshold: a lane's jsel-th smallest group minimum, max over the pair of lanes
+        // threshold: a lane's jsel-th smallest group minimum (negative values,
+        // from rounding, count as 0), max over the pair of lanes, as a key
         float tau[2];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            float v[32];
+            int v[32];
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) v[16 * q + r] = gmin[p][q][r];
+                for (int r = 0; r < 16; ++r) v[16 * q + r] = max(gmin[p][q][r], 0);
             sort_regs<32>(v);
-            float tl = v[31];
+            int tl = v[31];
 #pragma unroll
             for (int q = 0; q < 32; ++q)
                 if (q == a.jsel - 1) tl = v[q];
-            const float tt = fmaxf(tl, __shfl_xor(tl, 32));
-            tau[p] = fminf(tt, FLT_MAX);
+            tl = min(tl, 0x7F7FFFFF);  // +inf (too few landmarks) -> FLT_MAX
+            const float tt = fmaxf(__int_as_float(tl), __int_as_float(__shfl_xor(tl, 32)));
+            tau[p] = (tt >= FLT_MAX) ? FLT_MAX : tt - xnp[p];
         }
 
-        // ---------------- pass 2: candidate bitmaps (key <= tau) into LDS
-        for (int tp = 0; tp < W; ++tp) {
-            unsigned cur[2] = {0u, 0u};
+        // ---------------- pass 2: candidate bitmaps (key <= tau) into LDS.  The
+        // sign of tau - key is shifted in (1 = not a candidate) and the word
+        // complemented; a mask per lane marks the non-empty words.
+        unsigned long long nonempty[2] = {0ull, 0ull};
+        {
+            TileRegs<MODE, DC> cur, nxt;
+#if ESOM_TILE_PREFETCH
+            load_tile<MODE, DC>(a, 0, lane, cur);
+#endif
+            for (int tp = 0; tp < W; ++tp) {
+                unsigned word[2] = {0u, 0u};
 #pragma unroll
-            for (int half = 0; half < 2; ++half) {
-                f32x16 acc[2];
-                screen_tile<MODE, DC>(a, P, 2 * tp + half, lane, acc);
+                for (int half = 0; half < 2; ++half) {
+                    const int tn = 2 * tp + half + 1;
+#if ESOM_TILE_PREFETCH
+                    load_tile<MODE, DC>(a, tn < ntiles ? tn : ntiles - 1, lane, nxt);
+#else
+                    load_tile<MODE, DC>(a, tn - 1, lane, cur);
+#endif
+                    f32x16 acc[2];
+                    screen_tile<MODE, DC>(a, 2 * tp + half, lane, cur, P, acc);
 #pragma unroll
-                for (int p = 0; p < 2; ++p)
+                    for (int p = 0; p < 2; ++p)
 #pragma unroll
-                    for (int r = 0; r < 16; ++r)
-                        cur[p] = (cur[p] << 1) | (acc[p][r] <= tau[p] ? 1u : 0u);
+                        for (int r = 0; r < 16; ++r)
+                            word[p] = __builtin_amdgcn_alignbit(word[p], __float_as_uint(tau[p] - acc[p][r]), 31);
+#if ESOM_TILE_PREFETCH
+                    cur = nxt;
+#endif
+                }
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    word[p] = ~word[p];
+                    bitsL[(p * W + tp) * 64 + lane] = word[p];
+                    nonempty[p] |= (unsigned long long)(word[p] != 0u) << tp;
+                }
             }
-#pragma unroll
-            for (int p = 0; p < 2; ++p) bitsL[(p * W + tp) * 64 + lane] = cur[p];
         }
         if (h == 0) {
             tauL[i32] = tau[0];
@@ -472,6 +589,9 @@ __global__ void __launch_bounds__(512) embed_main(EmbedArgs a) {
             xnL[i32] = xnp[0];
             xnL[32 + i32] = xnp[1];
         }
+        // masks of lane (screen half h, point i32) for point groups p = 0, 1
+        maskL[(0 * 2 + h) * 32 + i32] = nonempty[0];
+        maskL[(1 * 2 + h) * 32 + i32] = nonempty[1];
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -492,46 +612,58 @@ __global__ void __launch_bounds__(512) embed_main(EmbedArgs a) {
         for (int q = 0; q < KP; ++q) sk[q] = INFINITY;
         double rej = INFINITY;
         int m = 0;
-        for (int tp = 0; tp < W; ++tp) {
-#pragma unroll
-            for (int hh = 0; hh < 2; ++hh) {
-                unsigned b = bitsL[(h * W + tp) * 64 + i32 + 32 * hh];
-                if (!valid) b = 0u;
-                while (b) {
-                    const int pos = __clz((int)b);
-                    b &= ~(0x80000000u >> pos);
-                    const int t = 2 * tp + (pos >> 4);
-                    const int r = pos & 15;
-                    const int j = 32 * t + 8 * (r >> 2) + 4 * hh + (r & 3);
-                    float acc = 0.f;
-                    if (a.lds_rows) {
-                        const float4 *Lr = reinterpret_cast<const float4 *>(rowsL + (size_t)j * RS);
-#pragma unroll
-                        for (int q = 0; q < DP / 4; ++q) {
-                            const float4 lv = Lr[q];
-                            const float e0 = x[4 * q] - lv.x, e1 = x[4 * q + 1] - lv.y;
-                            const float e2 = x[4 * q + 2] - lv.z, e3 = x[4 * q + 3] - lv.w;
-                            acc = fmaf(e0, e0, acc);
-                            acc = fmaf(e1, e1, acc);
-                            acc = fmaf(e2, e2, acc);
-                            acc = fmaf(e3, e3, acc);
-                        }
-                    } else {
-                        const float4 *Lr = reinterpret_cast<const float4 *>(a.Lpad + (size_t)j * DP);
-#pragma unroll
-                        for (int q = 0; q < DP / 4; ++q) {
-                            const float4 lv = Lr[q];
-                            const float e0 = x[4 * q] - lv.x, e1 = x[4 * q + 1] - lv.y;
-                            const float e2 = x[4 * q + 2] - lv.z, e3 = x[4 * q + 3] - lv.w;
-                            acc = fmaf(e0, e0, acc);
-                            acc = fmaf(e1, e1, acc);
-                            acc = fmaf(e2, e2, acc);
-                            acc = fmaf(e3, e3, acc);
-                        }
-                    }
-                    insert_sorted<KP>(sk, rej, pack_key(acc, j));
-                    ++m;
+        {
+            // Each lane walks its own candidates across all its words (one
+            // candidate per iteration), so the wave iterates max_l m_l times.
+            // The next non-empty word is read one word ahead.
+            unsigned long long mk0 = valid ? maskL[(h * 2 + 0) * 32 + i32] : 0ull;
+            unsigned long long mk1 = valid ? maskL[(h * 2 + 1) * 32 + i32] : 0ull;
+            int nhh = 0, ntp = 0;
+            unsigned nb = 0u;
+            next_word(mk0, mk1, bitsL + h * W * 64 + i32, nb, nhh, ntp);
+            unsigned b = 0u;
+            int chh = 0, ctp = 0;
+            for (;;) {
+                if (b == 0u) {
+                    if (nb == 0u) break;
+                    b = nb;
+                    chh = nhh;
+                    ctp = ntp;
+                    next_word(mk0, mk1, bitsL + h * W * 64 + i32, nb, nhh, ntp);
                 }
+                const int pos = __clz((int)b);
+                b &= ~(0x80000000u >> pos);
+                const int t = 2 * ctp + (pos >> 4);
+                const int r = pos & 15;
+                const int j = 32 * t + 8 * (r >> 2) + 4 * chh + (r & 3);
+                float acc = 0.f;
+                if (a.lds_rows) {
+                    const float4 *Lr = reinterpret_cast<const float4 *>(rowsL + (size_t)j * RS);
+#pragma unroll
+                    for (int q = 0; q < DP / 4; ++q) {
+                        const float4 lv = Lr[q];
+                        const float e0 = x[4 * q] - lv.x, e1 = x[4 * q + 1] - lv.y;
+                        const float e2 = x[4 * q + 2] - lv.z, e3 = x[4 * q + 3] - lv.w;
+                        acc = fmaf(e0, e0, acc);
+                        acc = fmaf(e1, e1, acc);
+                        acc = fmaf(e2, e2, acc);
+                        acc = fmaf(e3, e3, acc);
+                    }
+                } else {
+                    const float4 *Lr = reinterpret_cast<const float4 *>(a.Lpad + (size_t)j * DP);
+#pragma unroll
+                    for (int q = 0; q < DP / 4; ++q) {
+                        const float4 lv = Lr[q];
+                        const float e0 = x[4 * q] - lv.x, e1 = x[4 * q + 1] - lv.y;
+                        const float e2 = x[4 * q + 2] - lv.z, e3 = x[4 * q + 3] - lv.w;
+                        acc = fmaf(e0, e0, acc);
+                        acc = fmaf(e1, e1, acc);
+                        acc = fmaf(e2, e2, acc);
+                        acc = fmaf(e3, e3, acc);
+                    }
+                }
+                insert_sorted<KP>(sk, rej, pack_key(acc, j));
+                ++m;
             }
         }
         __builtin_amdgcn_wave_barrier();
@@ -554,7 +686,9 @@ __global__ void __launch_bounds__(512) embed_main(EmbedArgs a) {
             rhs -= 4.f * U32 * (fabsf(tau_p) + xn + E);
             const bool cert = (tau_p >= FLT_MAX) || (d2k * (1.f + (DP + 3) * U32) < rhs);
             if (!cert || m < a.k) reason |= R_UNCERT;
-            if (m > a.k && d2k1 - d2k <= 4.f * (DP + 3) * U32 * d2k1) reason |= R_NEARTIE;
+            // two rescored values are ordered correctly when their gap exceeds the sum
+            // of their rounding bounds, (d_pad + 3) u each
+            if (m > a.k && d2k1 - d2k <= 2.f * (DP + 3) * U32 * d2k1) reason |= R_NEARTIE;
         }
 
         // knn outputs (the exact path rewrites those of uncertified / near-tie points)

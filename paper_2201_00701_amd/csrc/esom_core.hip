@@ -36,19 +36,21 @@ __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
     }
 }
 
-// One thread per (padded) landmark: centred row, squared norm, MFMA operand
-// entries, the zero-padded FP32 copy for exact rescoring, and the norm max.
+// One wavefront per (padded) landmark, lanes over dimensions: centred row,
+// squared norm (FP64 wave sum), MFMA operand entries, the zero-padded FP32
+// copy for exact rescoring, and the norm maximum.
 __global__ void prep_landmarks(const float *__restrict__ L, int g, int gpad, int d, int dp,
                                int mode, const float *__restrict__ cent, void *__restrict__ A,
                                float *__restrict__ norms, float *__restrict__ Lpad,
                                float *__restrict__ lmax) {
-    const int j = blockIdx.x * blockDim.x + threadIdx.x;
+    const int j = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int lane = threadIdx.x & 63;
     if (j >= gpad) return;
     const int t = j / TILE, m = j % TILE;
     const int dc = dp / 16;
     const bool real = j < g;
     double nrm = 0.0;
-    for (int q = 0; q < dp; ++q) {
+    for (int q = lane; q < dp; q += 64) {
         const float lv = (real && q < d) ? L[(size_t)j * d + q] : 0.f;
         const float c = (real && q < d) ? lv - cent[q] : 0.f;
         nrm += (double)c * (double)c;
@@ -67,10 +69,15 @@ __global__ void prep_landmarks(const float *__restrict__ L, int g, int gpad, int
             reinterpret_cast<float *>(A)[((size_t)t * (dp / 2) + s) * 64 + 32 * hh + m] = a2;
         }
     }
-    // MFMA 32x32 output row m sits in lane half h = (m / 4) % 2, register r = 4 (m / 8) + m % 4
-    const int hh = (m / 4) % 2, r = 4 * (m / 8) + m % 4;
-    norms[((size_t)t * 2 + hh) * 16 + r] = real ? (float)nrm : INFINITY;
-    if (real) atomicMax(reinterpret_cast<unsigned *>(lmax), __float_as_uint((float)sqrt(nrm) * 1.0000002f));
+#pragma unroll
+    for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o);
+    if (lane == 0) {
+        // MFMA 32x32 output row m sits in lane half h = (m / 4) % 2, register r = 4 (m / 8) + m % 4
+        const int hh = (m / 4) % 2, r = 4 * (m / 8) + m % 4;
+        norms[((size_t)t * 2 + hh) * 16 + r] = real ? (float)nrm : INFINITY;
+        if (real)
+            atomicMax(reinterpret_cast<unsigned *>(lmax), __float_as_uint((float)sqrt(nrm) * 1.0000002f));
+    }
 }
 
 // Pair table inv2[u][v] = 1 / (2 |L_u - L_v|^2) (FP64 differences), -1 when zero.
@@ -91,7 +98,7 @@ hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long lo
     hipLaunchKernelGGL(prep_centroid, dim3(P.dp), dim3(256), 0, s, L, P.g, P.d, P.dp, P.cent,
                        P.lmax, counters, n_points);
     const int gpad = P.ntiles * TILE;
-    hipLaunchKernelGGL(prep_landmarks, dim3((gpad + 255) / 256), dim3(256), 0, s, L, P.g, gpad, P.d,
+    hipLaunchKernelGGL(prep_landmarks, dim3((gpad + 3) / 4), dim3(256), 0, s, L, P.g, gpad, P.d,
                        P.dp, mode, P.cent, P.A, P.norms, P.Lpad, P.lmax);
     const long long gg = (long long)P.g * P.g;
     hipLaunchKernelGGL(prep_pairs, dim3((unsigned)((gg + 255) / 256)), dim3(256), 0, s, L, P.g, P.d,
@@ -351,12 +358,15 @@ hipError_t launch_embed(const EmbedArgs &a0, int mode, int kp, int num_cus, size
     const int dc = a.dp / 16;
     const size_t wsm = (size_t)wave_smem_bytes(kp, a.npair_tiles);
     const size_t rows = ((size_t)a.g * (a.dp + 4) * 4 + 255) & ~(size_t)255;
-    // Stage the landmark rows in LDS when 8 waves still fit beside them,
-    // otherwise rescore from global memory with 4-wave blocks.
+    // Stage the landmark rows in LDS when a full block of waves (one block per
+    // CU: 3 waves per SIMD in BF16 mode, 2 in FP32 mode) still fits beside
+    // them; otherwise rescore from global memory with 4-wave blocks, several
+    // per CU.
+    const int max_wpb = main_max_block(mode, dc) / 64;
     int wpb;
-    if (rows + 8 * wsm <= lds_per_block) {
+    if (rows + (size_t)max_wpb * wsm <= lds_per_block) {
         a.lds_rows = 1;
-        wpb = 8;
+        wpb = max_wpb;
     } else {
         a.lds_rows = 0;
         wpb = (int)(lds_per_block / wsm);

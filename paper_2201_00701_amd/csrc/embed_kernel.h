@@ -53,8 +53,10 @@ constexpr double ILL_COND = 64.0;         // (tr/2)^2/det beyond this: exact pat
 
 // Largest block of the fused kernel: 12 waves (3 per SIMD, 168 registers per
 // lane) where the register budget of the instantiation allows it (BF16, padded
-// dimension <= 32), else 8 waves (256 registers).
-__host__ __device__ constexpr int main_max_block(int mode, int dc) { return (mode == 1 && dc <= 2) ? 768 : 512; }
+// dimension <= 32, k <= 16), else 8 waves (256 registers).
+__host__ __device__ constexpr int main_max_block(int mode, int dc, int kp) {
+    return (mode == 1 && dc <= 2 && kp <= 16) ? 768 : 512;
+}
 
 __device__ __forceinline__ unsigned bf16_bits_rne(float f) {
     unsigned u = __float_as_uint(f);
@@ -116,9 +118,9 @@ template <int KP>
 __device__ __forceinline__ void insert_sorted(double (&s)[KP], double &rej, double v) {
 #pragma unroll
     for (int q = 0; q < KP; ++q) {
-        const double lo = vmin64(s[q], v);
-        v = vmax64(s[q], v);
-        s[q] = lo;
+        const double hi = vmax64(s[q], v);
+        asm("v_min_f64 %0, %0, %1" : "+v"(s[q]) : "v"(v));  // in place: no copies of the list
+        v = hi;
     }
     rej = vmin64(rej, v);
 }
@@ -141,6 +143,9 @@ __device__ __forceinline__ void next_word(unsigned long long &mk0, unsigned long
         nb = row[ntp * 64 + 32];
     }
 }
+
+// LDS bytes of the block-wide centroid copy (padded dimension <= 128).
+constexpr int CENT_LDS_BYTES = 512;
 
 // Bytes of LDS one wave needs: candidate bitmaps (2 W words per lane), or for
 // KP > 16 the neighbour staging of the pair loop in the same space; then
@@ -237,7 +242,7 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
     for (int q = 0; q < KP; ++q) {
         d2q[q] = (q < a.k) ? key_d2(sk[q]) : 0.f;
         jq[q] = (q < a.k) ? key_idx(sk[q]) : 0;
-        dl[q] = sqrtf(d2q[q]);
+        dl[q] = __builtin_amdgcn_sqrtf(d2q[q]);
         if (q < a.k) mu = fmaf(dl[q], 1.f / (float)(q + 1), mu);
     }
     float d2k = d2q[0];
@@ -254,7 +259,10 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
         }
     }
     var /= a.Wk;
-    const float dk = sqrtf(d2k);
+    const float dk = __builtin_amdgcn_sqrtf(d2k);
+    // cutoff argument A (delta_q - delta_k) / delta_k; 1 - exp(.) loses only
+    // absolute accuracy ~u, negligible for a weight that is then tiny
+    const float cut_scale = a.cutoff * __builtin_amdgcn_rcpf(dk);
     const bool degenerate = d2q[0] == d2k;
     const bool flat = !(var > 1e-30f * mu * mu);
     const float isig = flat ? 0.f : a.boost * rsqrtf(var);
@@ -273,7 +281,7 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
         sq[q] = 0.f;
         if (q < a.k) {
             const float e = flat ? 1.f : __expf((mu - dl[q]) * isig);
-            const float c = a.use_cutoff ? -expm1f(a.cutoff * (dl[q] - dk) / dk) : 1.f;
+            const float c = a.use_cutoff ? 1.f - __expf((dl[q] - dk) * cut_scale) : 1.f;
             sq[q] = degenerate ? 0.f : e * c;
             ssum += sq[q];
             const float gs = a.gravity * sq[q];
@@ -285,19 +293,21 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
     }
     if (!(ssum > 0.f)) reason |= R_DEGEN;
 
-    // pairs (i < j among the neighbours with non-zero score)
-    const bool unit_adjust = a.adjust == 1.0f;
+    // pairs (i < j among the neighbours with non-zero score); d2i <= d2j
     bool ill = false;
+    const bool unit_adjust = a.adjust == 1.0f;
     auto pair_term = [&](float d2i, float si, float lxi, float lyi, float d2j, float sj, float lxj,
                          float lyj, float inv) {
         const float hx = lxj - lxi, hy = lyj - lyi;
         const float hh = fmaf(hx, hx, hy * hy);
         const bool skip = inv < 0.f || hh == 0.f;
         const float hs = skip ? 1.f : hh;
-        if (!skip && fmaxf(d2i, d2j) * inv > ILL_PAIR) ill = true;
+        ill |= !skip && d2j * inv > ILL_PAIR;
         const float D = fmaf(d2i - d2j, inv, 0.5f);
-        const float ihh = 1.f / hs;
-        const float q = skip ? 0.f : si * sj * (unit_adjust ? ihh : exp2f(-a.adjust * __log2f(hs)));
+        const float ihh = __builtin_amdgcn_rcpf(hs);
+        float w = ihh;
+        if (!unit_adjust) w = exp2f(-a.adjust * __log2f(hs));  // uniform branch
+        const float q = skip ? 0.f : si * sj * w;
         const float qh = q * ihh;
         const float t = fmaf(D, hs, fmaf(hx, lxi, hy * lyi));
         const float qhx = qh * hx, qhy = qh * hy;
@@ -410,7 +420,7 @@ __global__ void __launch_bounds__(256) embed_project(EmbedArgs a) {
 }
 
 template <int MODE, int DC, int KP>
-__global__ void __launch_bounds__(main_max_block(MODE, DC)) embed_main(EmbedArgs a) {
+__global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(EmbedArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int DP = 16 * DC;
     constexpr int RS = DP + 4;  // LDS row stride (floats): spreads rows over the banks
@@ -420,18 +430,21 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC)) embed_main(EmbedArgs
     const int h = lane >> 5;
     const int i32 = lane & 31;
     const int W = a.npair_tiles;
-    // Optional block-wide copy of the landmark rows for exact rescoring.
-    float *rowsL = reinterpret_cast<float *>(smem);
+    // Block-wide copies: the centroid (read for every point group), and
+    // optionally the landmark rows for exact rescoring.
+    float *centL = reinterpret_cast<float *>(smem);
+    float *rowsL = reinterpret_cast<float *>(smem + CENT_LDS_BYTES);
     const size_t rows_bytes = a.lds_rows ? (((size_t)a.g * RS * 4 + 255) & ~(size_t)255) : 0;
+    for (int e = threadIdx.x; e < DP; e += blockDim.x) centL[e] = e < a.d ? a.cent[e] : 0.f;
     if (a.lds_rows) {
         for (int e = threadIdx.x; e < a.g * (DP / 4); e += blockDim.x) {
             const int j = e / (DP / 4), q = e % (DP / 4);
             reinterpret_cast<float4 *>(rowsL + (size_t)j * RS)[q] =
                 reinterpret_cast<const float4 *>(a.Lpad + (size_t)j * DP)[q];
         }
-        __syncthreads();
     }
-    unsigned char *wsm = smem + rows_bytes + (size_t)wave * wave_smem_bytes(KP, W);
+    __syncthreads();
+    unsigned char *wsm = smem + CENT_LDS_BYTES + rows_bytes + (size_t)wave * wave_smem_bytes(KP, W);
     unsigned *bitsL = reinterpret_cast<unsigned *>(wsm);
     float *nbD2 = reinterpret_cast<float *>(wsm);
     float *nbS = nbD2 + KP * 64;
@@ -463,11 +476,25 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC)) embed_main(EmbedArgs
 #pragma unroll
                 for (int c = 0; c < DC; ++c) {
                     unsigned w[4];
+                    float4 xv[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
+                    if (a.x_vec4 && valid) {
+                        const float4 *x4 = reinterpret_cast<const float4 *>(xr + 16 * c + 8 * h);
+                        const float4 *c4 = reinterpret_cast<const float4 *>(centL + 16 * c + 8 * h);
+#pragma unroll
+                        for (int u = 0; u < 2; ++u) {
+                            const float4 q = x4[u], cv = c4[u];
+                            xv[u] = make_float4(q.x - cv.x, q.y - cv.y, q.z - cv.z, q.w - cv.w);
+                        }
+                    }
 #pragma unroll
                     for (int e = 0; e < 8; e += 2) {
                         const int d0 = 16 * c + 8 * h + e;
-                        const float v0 = (valid && d0 < a.d) ? xr[d0] - a.cent[d0] : 0.f;
-                        const float v1 = (valid && d0 + 1 < a.d) ? xr[d0 + 1] - a.cent[d0 + 1] : 0.f;
+                        const float4 &xq = xv[e >> 2];
+                        float v0 = (e & 2) ? xq.z : xq.x, v1 = (e & 2) ? xq.w : xq.y;
+                        if (!a.x_vec4) {
+                            v0 = (valid && d0 < a.d) ? xr[d0] - centL[d0] : 0.f;
+                            v1 = (valid && d0 + 1 < a.d) ? xr[d0 + 1] - centL[d0 + 1] : 0.f;
+                        }
                         part = fmaf(v0, v0, part);
                         part = fmaf(v1, v1, part);
                         w[e >> 1] = bf16_bits_rne(v0) | (bf16_bits_rne(v1) << 16);
@@ -479,7 +506,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC)) embed_main(EmbedArgs
 #pragma unroll
                 for (int s = 0; s < 8 * DC; ++s) {
                     const int dd = 2 * s + h;
-                    const float v = (valid && dd < a.d) ? xr[dd] - a.cent[dd] : 0.f;
+                    const float v = (valid && dd < a.d) ? xr[dd] - centL[dd] : 0.f;
                     part = fmaf(v, v, part);
                     P.b[p][s] = v;
                 }
@@ -604,8 +631,19 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC)) embed_main(EmbedArgs
         float x[DP];
         {
             const float *xr = a.X + (valid ? pi : 0) * a.ldx;
+            if (a.x_vec4) {
 #pragma unroll
-            for (int t = 0; t < DP; ++t) x[t] = (valid && t < a.d) ? xr[t] : 0.f;
+                for (int t = 0; t < DP / 4; ++t) {
+                    const float4 v = reinterpret_cast<const float4 *>(xr)[t];
+                    x[4 * t] = v.x;
+                    x[4 * t + 1] = v.y;
+                    x[4 * t + 2] = v.z;
+                    x[4 * t + 3] = v.w;
+                }
+            } else {
+#pragma unroll
+                for (int t = 0; t < DP; ++t) x[t] = (t < a.d) ? xr[t < a.d ? t : a.d - 1] : 0.f;
+            }
         }
         double sk[KP];
 #pragma unroll
@@ -623,19 +661,24 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC)) embed_main(EmbedArgs
             next_word(mk0, mk1, bitsL + h * W * 64 + i32, nb, nhh, ntp);
             unsigned b = 0u;
             int chh = 0, ctp = 0;
+            // The loop is wave-uniform (it ends when no lane has a candidate
+            // left); a lane without one rescores landmark 0 and inserts +inf,
+            // which leaves its list unchanged.  Keeping the insertion out of
+            // divergent control flow keeps the list in place in registers.
             for (;;) {
-                if (b == 0u) {
-                    if (nb == 0u) break;
+                if (b == 0u && nb != 0u) {
                     b = nb;
                     chh = nhh;
                     ctp = ntp;
                     next_word(mk0, mk1, bitsL + h * W * 64 + i32, nb, nhh, ntp);
                 }
+                const bool act = b != 0u;
+                if (__ballot(act) == 0ull) break;
                 const int pos = __clz((int)b);
                 b &= ~(0x80000000u >> pos);
                 const int t = 2 * ctp + (pos >> 4);
                 const int r = pos & 15;
-                const int j = 32 * t + 8 * (r >> 2) + 4 * chh + (r & 3);
+                const int j = act ? 32 * t + 8 * (r >> 2) + 4 * chh + (r & 3) : 0;
                 float acc = 0.f;
                 if (a.lds_rows) {
                     const float4 *Lr = reinterpret_cast<const float4 *>(rowsL + (size_t)j * RS);
@@ -662,8 +705,8 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC)) embed_main(EmbedArgs
                         acc = fmaf(e3, e3, acc);
                     }
                 }
-                insert_sorted<KP>(sk, rej, pack_key(acc, j));
-                ++m;
+                insert_sorted<KP>(sk, rej, act ? pack_key(acc, j) : (double)INFINITY);
+                m += act ? 1 : 0;
             }
         }
         __builtin_amdgcn_wave_barrier();

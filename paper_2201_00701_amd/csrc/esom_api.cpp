@@ -232,6 +232,8 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
     a.counters = c->counters;
     a.knn_only = knn_only;
     a.knn_mark = knn_mark;
+    a.x_vec4 = (d == pl.dp && ldx % 4 == 0 && ((uintptr_t)X & 15) == 0 &&
+                ((uintptr_t)pr.cent & 15) == 0) ? 1 : 0;
     if (what == EMBED_PROJECT && pl.kp != 0) {
         e = launch_project(a, pl.kp, c->num_cus, s);
         if (e != hipSuccess) return hip_fail(e, "projection kernel launch");

@@ -362,18 +362,18 @@ hipError_t launch_embed(const EmbedArgs &a0, int mode, int kp, int num_cus, size
     // CU: 3 waves per SIMD in BF16 mode, 2 in FP32 mode) still fits beside
     // them; otherwise rescore from global memory with 4-wave blocks, several
     // per CU.
-    const int max_wpb = main_max_block(mode, dc) / 64;
+    const int max_wpb = main_max_block(mode, dc, kp) / 64;
     int wpb;
-    if (rows + (size_t)max_wpb * wsm <= lds_per_block) {
+    if (CENT_LDS_BYTES + rows + (size_t)max_wpb * wsm <= lds_per_block) {
         a.lds_rows = 1;
         wpb = max_wpb;
     } else {
         a.lds_rows = 0;
-        wpb = (int)(lds_per_block / wsm);
+        wpb = (int)((lds_per_block - CENT_LDS_BYTES) / wsm);
         if (wpb > 4) wpb = 4;
         if (wpb < 1) wpb = 1;
     }
-    const size_t smem = (a.lds_rows ? rows : 0) + (size_t)wpb * wsm;
+    const size_t smem = CENT_LDS_BYTES + (a.lds_rows ? rows : 0) + (size_t)wpb * wsm;
     const int block = 64 * wpb;
     if (mode == 0) {
         if (kp == 8) return launch_main_m0_kp8(a, dc, block, smem, num_cus, s);

@@ -36,10 +36,6 @@
 
 #include "esom_internal.h"
 
-#ifndef ESOM_TILE_PREFETCH
-#define ESOM_TILE_PREFETCH 0
-#endif
-
 namespace esom {
 
 typedef float f32x16 __attribute__((ext_vector_type(16)));
@@ -74,6 +70,16 @@ __device__ __forceinline__ float key_d2(double v) {
 }
 __device__ __forceinline__ int key_idx(double v) {
     return (int)((unsigned long long)__double_as_longlong(v) & 0x1FFFull);
+}
+
+// Upper bound of the exact k-th nearest squared distance from the rescored
+// k-th value d2k: each of the first k rescored values is within (d_pad+3)u of
+// its exact value, so k landmarks lie within d2k (1 + 2 (d_pad+3) u); the
+// factor 4 leaves room for the FP64 distances of the exact path.  +inf when
+// fewer than k candidates were rescored (d2k = +inf).
+__device__ __forceinline__ float kth_bound(float d2k, int dp) {
+    const float t = d2k * (1.f + 4.f * (float)(dp + 3) * U32);
+    return t < FLT_MAX ? t : INFINITY;
 }
 
 // Ascending bitonic sort of N non-negative floats given as their bit
@@ -143,6 +149,11 @@ __device__ __forceinline__ void next_word(unsigned long long &mk0, unsigned long
         nb = row[ntp * 64 + 32];
     }
 }
+
+template <bool B>
+struct BoolTag {
+    static constexpr bool value = B;
+};
 
 // LDS bytes of the block-wide centroid copy (padded dimension <= 128).
 constexpr int CENT_LDS_BYTES = 512;
@@ -296,8 +307,10 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
     // pairs (i < j among the neighbours with non-zero score); d2i <= d2j
     bool ill = false;
     const bool unit_adjust = a.adjust == 1.0f;
-    auto pair_term = [&](float d2i, float si, float lxi, float lyi, float d2j, float sj, float lxj,
-                         float lyj, float inv) {
+    // unit: adjust == 1 (weight 1 / |h|^2), as a compile-time tag so that the
+    // two variants of the pair loop are separate code
+    auto pair_term = [&](auto unit, float d2i, float si, float lxi, float lyi, float d2j, float sj,
+                         float lxj, float lyj, float inv) {
         const float hx = lxj - lxi, hy = lyj - lyi;
         const float hh = fmaf(hx, hx, hy * hy);
         const bool skip = inv < 0.f || hh == 0.f;
@@ -305,8 +318,11 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
         ill |= !skip && d2j * inv > ILL_PAIR;
         const float D = fmaf(d2i - d2j, inv, 0.5f);
         const float ihh = __builtin_amdgcn_rcpf(hs);
-        float w = ihh;
-        if (!unit_adjust) w = exp2f(-a.adjust * __log2f(hs));  // uniform branch
+        float w;
+        if constexpr (decltype(unit)::value)
+            w = ihh;
+        else
+            w = exp2f(-a.adjust * __log2f(hs));
         const float q = skip ? 0.f : si * sj * w;
         const float qh = q * ihh;
         const float t = fmaf(D, hs, fmaf(hx, lxi, hy * lyi));
@@ -317,6 +333,7 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
         r0 = fmaf(qhx, t, r0);
         r1 = fmaf(qhy, t, r1);
     };
+    auto run_pairs = [&](auto unit) {
     if constexpr (KP <= 16) {
         // neighbour data in registers; each row of pair-table loads is issued together
 #pragma unroll
@@ -329,8 +346,8 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
 #pragma unroll
                 for (int qj = qi + 1; qj < KP; ++qj)
                     if (qj < a.kact)
-                        pair_term(d2q[qi], sq[qi], lxq[qi], lyq[qi], d2q[qj], sq[qj], lxq[qj], lyq[qj],
-                                  inv[qj]);
+                        pair_term(unit, d2q[qi], sq[qi], lxq[qi], lyq[qi], d2q[qj], sq[qj], lxq[qj],
+                                  lyq[qj], inv[qj]);
             }
         }
     } else {
@@ -366,11 +383,16 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    pair_term(d2i, si, lxi, lyi, d2j[u], sj[u], lxj[u], lyj[u], inv[u]);
+                    pair_term(unit, d2i, si, lxi, lyi, d2j[u], sj[u], lxj[u], lyj[u], inv[u]);
             }
         }
         __builtin_amdgcn_wave_barrier();
     }
+    };
+    if (unit_adjust)
+        run_pairs(BoolTag<true>{});
+    else
+        run_pairs(BoolTag<false>{});
     // 2x2 solve in FP64 (Cramer's rule)
     const double m00 = M00, m01 = M01, m11 = M11, rr0 = r0, rr1 = r1;
     const double det = m00 * m11 - m01 * m01;
@@ -410,11 +432,17 @@ __global__ void __launch_bounds__(256) embed_project(EmbedArgs a) {
                 sk[q] = pack_key(a.knn_d2[pi * a.k + q], a.knn_idx[pi * a.k + q]);
         }
         unsigned reason = (valid && a.knn_mark && a.knn_mark[pi]) ? (unsigned)R_NEARTIE : 0u;
+        float d2k = INFINITY;
+#pragma unroll
+        for (int q = 0; q < KP; ++q)
+            if (q == a.k - 1) d2k = key_d2(sk[q]);
+        const float thr = kth_bound(d2k, a.dp);
         reason = project_point<KP>(a, sk, lane, valid, pi, reason, nbD2, nbS, nbI);
         if (valid && reason) {
             const unsigned long long slot = atomicAdd(&a.counters[C_FB_LEN], 1ull);
             a.fb_list[slot] = (int32_t)pi;
             a.fb_reason[slot] = (uint8_t)reason;
+            a.fb_thresh[slot] = thr;
         }
     }
 }
@@ -515,8 +543,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         }
 
         // ---------------- pass 1: group minima of the approximate squared distances
-        // key + |x - c|^2 (bit patterns: integer minima, no NaN quieting).  The
-        // tiles are streamed with the next one's operands loaded ahead.
+        // key + |x - c|^2 (bit patterns: integer minima, no NaN quieting).
         int gmin[2][2][16];
 #pragma unroll
         for (int p = 0; p < 2; ++p)
@@ -524,37 +551,31 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             for (int q = 0; q < 2; ++q)
 #pragma unroll
                 for (int r = 0; r < 16; ++r) gmin[p][q][r] = 0x7F800000;
-        const int ntiles = 2 * W;
+        auto pass1_consume = [&](const f32x16 (&acc)[2], int half) {
+#pragma unroll
+            for (int p = 0; p < 2; ++p)
+#pragma unroll
+                for (int r = 0; r < 16; ++r)
+                    gmin[p][half][r] = min(gmin[p][half][r], __float_as_int(acc[p][r] + xnp[p]));
+        };
         {
-            TileRegs<MODE, DC> cur, nxt;
-#if ESOM_TILE_PREFETCH
-            load_tile<MODE, DC>(a, 0, lane, cur);
-#endif
+            TileRegs<MODE, DC> T;
             for (int tp = 0; tp < W; ++tp) {
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
-                    const int tn = 2 * tp + half + 1;
-#if ESOM_TILE_PREFETCH
-                    load_tile<MODE, DC>(a, tn < ntiles ? tn : ntiles - 1, lane, nxt);
-#else
-                    load_tile<MODE, DC>(a, tn - 1, lane, cur);
-#endif
                     f32x16 acc[2];
-                    screen_tile<MODE, DC>(a, 2 * tp + half, lane, cur, P, acc);
-#pragma unroll
-                    for (int p = 0; p < 2; ++p)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r)
-                            gmin[p][half][r] = min(gmin[p][half][r], __float_as_int(acc[p][r] + xnp[p]));
-#if ESOM_TILE_PREFETCH
-                    cur = nxt;
-#endif
+                    load_tile<MODE, DC>(a, 2 * tp + half, lane, T);
+                    screen_tile<MODE, DC>(a, 2 * tp + half, lane, T, P, acc);
+                    pass1_consume(acc, half);
                 }
             }
         }
-        // threshold: a lane's jsel-th smallest group minimum (negative values,
-        // from rounding, count as 0), max over the pair of lanes, as a key
-        float tau[2];
+        // thresholds: a lane's jsel-th smallest group minimum (negative values,
+        // from rounding, count as 0), as a key.  BF16 mode screens each half of
+        // the landmarks against its own lane's value (each half then holds at
+        // least jsel candidates, 2 jsel >= C in all) and certifies against the
+        // smaller of the two; FP32 mode (C close to k) uses the larger for both.
+        float tau[2], taucert[2];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             int v[32];
@@ -568,8 +589,11 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             for (int q = 0; q < 32; ++q)
                 if (q == a.jsel - 1) tl = v[q];
             tl = min(tl, 0x7F7FFFFF);  // +inf (too few landmarks) -> FLT_MAX
-            const float tt = fmaxf(__int_as_float(tl), __int_as_float(__shfl_xor(tl, 32)));
-            tau[p] = (tt >= FLT_MAX) ? FLT_MAX : tt - xnp[p];
+            const float own = __int_as_float(tl), oth = __int_as_float(__shfl_xor(tl, 32));
+            const float tb = MODE == 1 ? own : fmaxf(own, oth);
+            const float tc = MODE == 1 ? fminf(own, oth) : fmaxf(own, oth);
+            tau[p] = (tb >= FLT_MAX) ? FLT_MAX : tb - xnp[p];
+            taucert[p] = (tc >= FLT_MAX) ? FLT_MAX : tc - xnp[p];
         }
 
         // ---------------- pass 2: candidate bitmaps (key <= tau) into LDS.  The
@@ -577,42 +601,37 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         // complemented; a mask per lane marks the non-empty words.
         unsigned long long nonempty[2] = {0ull, 0ull};
         {
-            TileRegs<MODE, DC> cur, nxt;
-#if ESOM_TILE_PREFETCH
-            load_tile<MODE, DC>(a, 0, lane, cur);
-#endif
-            for (int tp = 0; tp < W; ++tp) {
-                unsigned word[2] = {0u, 0u};
+            unsigned word[2] = {0u, 0u};
+            auto pass2_consume = [&](const f32x16 (&acc)[2]) {
 #pragma unroll
-                for (int half = 0; half < 2; ++half) {
-                    const int tn = 2 * tp + half + 1;
-#if ESOM_TILE_PREFETCH
-                    load_tile<MODE, DC>(a, tn < ntiles ? tn : ntiles - 1, lane, nxt);
-#else
-                    load_tile<MODE, DC>(a, tn - 1, lane, cur);
-#endif
-                    f32x16 acc[2];
-                    screen_tile<MODE, DC>(a, 2 * tp + half, lane, cur, P, acc);
+                for (int p = 0; p < 2; ++p)
 #pragma unroll
-                    for (int p = 0; p < 2; ++p)
-#pragma unroll
-                        for (int r = 0; r < 16; ++r)
-                            word[p] = __builtin_amdgcn_alignbit(word[p], __float_as_uint(tau[p] - acc[p][r]), 31);
-#if ESOM_TILE_PREFETCH
-                    cur = nxt;
-#endif
-                }
+                    for (int r = 0; r < 16; ++r)
+                        word[p] = __builtin_amdgcn_alignbit(word[p], __float_as_uint(tau[p] - acc[p][r]), 31);
+            };
+            auto pass2_store = [&](int tp) {
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
-                    word[p] = ~word[p];
-                    bitsL[(p * W + tp) * 64 + lane] = word[p];
-                    nonempty[p] |= (unsigned long long)(word[p] != 0u) << tp;
+                    const unsigned wd = ~word[p];
+                    bitsL[(p * W + tp) * 64 + lane] = wd;
+                    nonempty[p] |= (unsigned long long)(wd != 0u) << tp;
                 }
+            };
+            TileRegs<MODE, DC> T;
+            for (int tp = 0; tp < W; ++tp) {
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    f32x16 acc[2];
+                    load_tile<MODE, DC>(a, 2 * tp + half, lane, T);
+                    screen_tile<MODE, DC>(a, 2 * tp + half, lane, T, P, acc);
+                    pass2_consume(acc);
+                }
+                pass2_store(tp);
             }
         }
         if (h == 0) {
-            tauL[i32] = tau[0];
-            tauL[32 + i32] = tau[1];
+            tauL[i32] = taucert[0];
+            tauL[32 + i32] = taucert[1];
             xnL[i32] = xnp[0];
             xnL[32 + i32] = xnp[1];
         }
@@ -719,6 +738,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             if (q == a.k) d2k1 = key_d2(sk[q]);
         }
         if (a.k >= KP) d2k1 = (rej < INFINITY) ? key_d2(rej) : INFINITY;
+        const float thr = kth_bound(m >= a.k ? d2k : INFINITY, DP);
 
         unsigned reason = 0;
         {
@@ -754,6 +774,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             const unsigned long long slot = atomicAdd(&a.counters[C_FB_LEN], 1ull);
             a.fb_list[slot] = (int32_t)pi;
             a.fb_reason[slot] = (uint8_t)reason;
+            a.fb_thresh[slot] = thr;
         }
         st_cand += valid ? (unsigned long long)m : 0ull;
     }

@@ -96,6 +96,7 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp) {
     sc.prep.lmax = static_cast<float *>(take(sizeof(float)));
     sc.fb_list = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     sc.fb_reason = static_cast<uint8_t *>(take((size_t)(n > 0 ? n : 1)));
+    sc.fb_thresh = static_cast<float *>(take(sizeof(float) * (size_t)(n > 0 ? n : 1)));
     return off;
 }
 
@@ -229,6 +230,7 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
     a.knn_d2 = knn_d2;
     a.fb_list = c->sc.fb_list;
     a.fb_reason = c->sc.fb_reason;
+    a.fb_thresh = c->sc.fb_thresh;
     a.counters = c->counters;
     a.knn_only = knn_only;
     a.knn_mark = knn_mark;

@@ -80,17 +80,35 @@ __global__ void prep_landmarks(const float *__restrict__ L, int g, int gpad, int
     }
 }
 
-// Pair table inv2[u][v] = 1 / (2 |L_u - L_v|^2) (FP64 differences), -1 when zero.
-__global__ void prep_pairs(const float *__restrict__ L, int g, int d, float *__restrict__ inv2) {
-    const long long e = (long long)blockIdx.x * blockDim.x + threadIdx.x;
-    if (e >= (long long)g * g) return;
-    const int u = (int)(e / g), v = (int)(e % g);
+// Pair table inv2[u][v] = 1 / (2 |L_u - L_v|^2) (FP64 differences), -1 when
+// zero.  A 256-thread block computes a 16 x 16 tile of pairs from the two
+// 16-row slices of L staged in LDS (row stride d + 1 floats: no bank
+// conflicts between the 16 rows a wave reads); rows are read and the table
+// written coalesced.
+constexpr int PAIR_TILE = 16;
+
+__global__ void __launch_bounds__(256) prep_pairs(const float *__restrict__ L, int g, int d,
+                                                  float *__restrict__ inv2) {
+    extern __shared__ float prs[];  // 2 x PAIR_TILE x (d + 1)
+    const int ntu = (g + PAIR_TILE - 1) / PAIR_TILE;
+    const int u0 = (blockIdx.x / ntu) * PAIR_TILE, v0 = (blockIdx.x % ntu) * PAIR_TILE;
+    const int rs = d + 1;
+    float *Lu = prs, *Lv = prs + PAIR_TILE * rs;
+    for (int e = threadIdx.x; e < PAIR_TILE * d; e += blockDim.x) {
+        const int r = e / d, q = e % d;
+        Lu[r * rs + q] = u0 + r < g ? L[(size_t)(u0 + r) * d + q] : 0.f;
+        Lv[r * rs + q] = v0 + r < g ? L[(size_t)(v0 + r) * d + q] : 0.f;
+    }
+    __syncthreads();
+    const int ty = threadIdx.x / PAIR_TILE, tx = threadIdx.x % PAIR_TILE;
+    const int u = u0 + ty, v = v0 + tx;
+    if (u >= g || v >= g) return;
     double s = 0.0;
     for (int q = 0; q < d; ++q) {
-        const double df = (double)L[(size_t)v * d + q] - (double)L[(size_t)u * d + q];
-        s += df * df;
+        const double df = (double)Lv[tx * rs + q] - (double)Lu[ty * rs + q];
+        s = fma(df, df, s);
     }
-    inv2[e] = s > 0.0 ? (float)(0.5 / s) : -1.f;
+    inv2[(size_t)u * g + v] = s > 0.0 ? (float)(0.5 / s) : -1.f;
 }
 
 hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long long *counters,
@@ -100,9 +118,9 @@ hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long lo
     const int gpad = P.ntiles * TILE;
     hipLaunchKernelGGL(prep_landmarks, dim3((gpad + 3) / 4), dim3(256), 0, s, L, P.g, gpad, P.d,
                        P.dp, mode, P.cent, P.A, P.norms, P.Lpad, P.lmax);
-    const long long gg = (long long)P.g * P.g;
-    hipLaunchKernelGGL(prep_pairs, dim3((unsigned)((gg + 255) / 256)), dim3(256), 0, s, L, P.g, P.d,
-                       P.inv2);
+    const int ntu = (P.g + PAIR_TILE - 1) / PAIR_TILE;
+    hipLaunchKernelGGL(prep_pairs, dim3((unsigned)(ntu * ntu)), dim3(256),
+                       sizeof(float) * 2 * PAIR_TILE * (P.d + 1), s, L, P.g, P.d, P.inv2);
     return hipGetLastError();
 }
 
@@ -127,111 +145,165 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Recomputes points exactly in FP64, one wavefront (block of 64) per point:
-// all g distances from the coordinates into LDS, the k (+1) nearest by
-// repeated wave-wide (distance, index) minima, the scores, every pair's
-// segment projection from the coordinates spread over the lanes, and
-// Cramer's rule; the centroid of the neighbours for degenerate
-// neighbourhoods.  all_points = 1 processes every point (shapes outside the
-// fast kernels), otherwise the fast kernel's list.
-__global__ void __launch_bounds__(64) embed_exact(EmbedArgs a, int all_points) {
+// Recomputes points exactly in FP64, one block of EX_THREADS per point:
+//  1. all g distances from FP64 differences into LDS; the landmarks within
+//     the point's k-th distance bound (fb_thresh) are collected;
+//  2. the k nearest by (distance, index): each collected landmark's rank is
+//     counted against the others (few of them); with no usable bound (or too
+//     many within it) one wavefront takes k repeated (distance, index) minima
+//     over all g instead;
+//  3. the scores; every pair's segment projection from the coordinates,
+//     spread over the threads; block sums;
+//  4. Cramer's rule, or the centroid of the neighbours' 2-D positions for a
+//     degenerate neighbourhood.
+// all_points = 1 processes every point (shapes outside the fast kernels),
+// otherwise the fast kernel's list.
+constexpr int EX_THREADS = 256;
+constexpr int EX_SEL_CAP = 256;  // collected landmarks ranked by counting
+
+__device__ __forceinline__ bool lex_less(double a, int ia, double b, int ib) {
+    return a < b || (a == b && ia < ib);
+}
+
+__global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_points) {
     extern __shared__ __align__(16) unsigned char esm[];
     double *dist = reinterpret_cast<double *>(esm);        // g
-    double *xs = dist + a.g;                                // d
-    double *sel_d = xs + a.d;                               // k + 1
-    double *sc = sel_d + (ESOM_MAX_K + 1);                  // k
-    int *sel_j = reinterpret_cast<int *>(sc + ESOM_MAX_K);  // k + 1
-    const int lane = threadIdx.x;
+    double *xs = dist + a.g;                                // dp (zero beyond d)
+    double *sel_d = xs + a.dp;                              // k
+    double *sc = sel_d + ESOM_MAX_K;                        // k
+    double *red = sc + ESOM_MAX_K;                          // 6 per wave
+    int *sel_j = reinterpret_cast<int *>(red + 6 * (EX_THREADS / 64));  // k
+    int *cand = sel_j + ESOM_MAX_K;                         // EX_SEL_CAP
+    int *flags = cand + EX_SEL_CAP;                         // [0] count, [1] bad
+    const int tid = threadIdx.x;
+    const int lane = tid & 63;
+    const int wv = tid >> 6;
     const long long cnt = all_points
                               ? a.n
                               : (long long)min(a.counters[C_FB_LEN], (unsigned long long)a.n);
     const int k = a.k;
-    const int m = k + 1 <= a.g ? k + 1 : a.g;
+    const int g = a.g;
     unsigned long long n_fb = 0, n_unc = 0, n_tie = 0, n_ill = 0, n_deg = 0;
     for (long long e = blockIdx.x; e < cnt; e += gridDim.x) {
         const long long pi = all_points ? e : (long long)a.fb_list[e];
         const unsigned reason = all_points ? 0u : (unsigned)a.fb_reason[e];
+        const double thr = all_points ? (double)INFINITY : (double)a.fb_thresh[e];
         ++n_fb;
         n_unc += (reason & R_UNCERT) ? 1 : 0;
         n_tie += (reason & R_NEARTIE) ? 1 : 0;
         n_ill += (reason & R_ILLCOND) ? 1 : 0;
         const float *xr = a.X + pi * a.ldx;
-        for (int q = lane; q < a.d; q += 64) xs[q] = (double)xr[q];
+        for (int q = tid; q < a.dp; q += EX_THREADS) xs[q] = q < a.d ? (double)xr[q] : 0.0;
+        if (tid == 0) {
+            flags[0] = 0;
+            flags[1] = 0;
+        }
         __syncthreads();
-        for (int j = lane; j < a.g; j += 64) {
-            const float *Lj = a.Lpad + (size_t)j * a.dp;
+        // 1. distances; collect the landmarks within the bound
+        for (int j = tid; j < g; j += EX_THREADS) {
+            const float4 *Lj = reinterpret_cast<const float4 *>(a.Lpad + (size_t)j * a.dp);
             double s = 0.0;
-            for (int q = 0; q < a.d; ++q) {
-                const double df = xs[q] - (double)Lj[q];
-                s = fma(df, df, s);
+            for (int q = 0; q < a.dp / 4; ++q) {
+                const float4 v = Lj[q];
+                const double d0 = xs[4 * q] - (double)v.x, d1 = xs[4 * q + 1] - (double)v.y;
+                const double d2 = xs[4 * q + 2] - (double)v.z, d3 = xs[4 * q + 3] - (double)v.w;
+                s = fma(d0, d0, s);
+                s = fma(d1, d1, s);
+                s = fma(d2, d2, s);
+                s = fma(d3, d3, s);
             }
             dist[j] = s;
+            if (s <= thr) {
+                const int slot = atomicAdd(&flags[0], 1);
+                if (slot < EX_SEL_CAP) cand[slot] = j;
+            }
         }
         __syncthreads();
-        // m smallest by (distance, index); taken entries become NaN (never minimal)
-        bool bad = false;
-        for (int r = 0; r < m; ++r) {
-            double bv = INFINITY;
-            int bj = 0x7fffffff;
-            for (int j = lane; j < a.g; j += 64) {
-                const double v = dist[j];
-                if (v < bv || (v == bv && j < bj)) {
-                    bv = v;
-                    bj = j;
+        // 2. the k nearest, sorted by (distance, index)
+        const int nc = flags[0];
+        if (nc >= k && nc <= EX_SEL_CAP) {
+            for (int c = tid; c < nc; c += EX_THREADS) {
+                const int jc = cand[c];
+                const double dc = dist[jc];
+                int rank = 0;
+                for (int o = 0; o < nc; ++o) {
+                    const int jo = cand[o];
+                    rank += lex_less(dist[jo], jo, dc, jc) ? 1 : 0;
+                }
+                if (rank < k) {
+                    sel_d[rank] = dc;
+                    sel_j[rank] = jc;
                 }
             }
-            wave_argmin(bv, bj);
-            if (bj == 0x7fffffff) bad = true;
-            if (lane == 0) {
-                sel_d[r] = bv;
-                sel_j[r] = bj;
-                if (bj != 0x7fffffff) dist[bj] = NAN;
+        } else if (wv == 0) {
+            // k repeated minima over all g; taken entries become NaN (never minimal)
+            for (int r = 0; r < k; ++r) {
+                double bv = INFINITY;
+                int bj = 0x7fffffff;
+                for (int j = lane; j < g; j += 64) {
+                    const double v = dist[j];
+                    if (v < bv || (v == bv && j < bj)) {
+                        bv = v;
+                        bj = j;
+                    }
+                }
+                wave_argmin(bv, bj);
+                if (lane == 0) {
+                    sel_d[r] = bv;
+                    sel_j[r] = bj;
+                    if (bj != 0x7fffffff)
+                        dist[bj] = NAN;
+                    else
+                        flags[1] = 1;
+                }
+                __builtin_amdgcn_fence(__ATOMIC_RELEASE, "workgroup");
+                __builtin_amdgcn_wave_barrier();
+                __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "workgroup");
             }
-            __syncthreads();
         }
+        __syncthreads();
+        const bool bad = flags[1] != 0;
         // Neighbours of points listed only for the projection (ill-conditioned,
         // degenerate) were already certified by the fast kernel: keep its outputs.
         const bool hd_reason = all_points || (reason & (R_UNCERT | R_NEARTIE)) || a.knn_only;
-        if (lane < k && hd_reason) {
-            if (a.knn_idx) a.knn_idx[pi * k + lane] = bad ? -1 : sel_j[lane];
-            if (a.knn_d2) a.knn_d2[pi * k + lane] = (float)sel_d[lane];
+        if (tid < k && hd_reason) {
+            if (a.knn_idx) a.knn_idx[pi * k + tid] = bad ? -1 : sel_j[tid];
+            if (a.knn_d2) a.knn_d2[pi * k + tid] = (float)sel_d[tid];
         }
-        if (lane == 0 && a.knn_mark && hd_reason) a.knn_mark[pi] = 1;
-        if (a.knn_only) continue;
+        if (tid == 0 && a.knn_mark && hd_reason) a.knn_mark[pi] = 1;
+        if (a.knn_only) {
+            __syncthreads();
+            continue;
+        }
         if (bad) {
-            if (lane == 0) {
+            if (tid == 0) {
                 a.out[2 * pi] = NAN;
                 a.out[2 * pi + 1] = NAN;
             }
+            __syncthreads();
             continue;
         }
-        // scores (every lane computes the neighbourhood statistics)
-        const double dl0 = sqrt(sel_d[0]), dlk = sqrt(sel_d[k - 1]);
-        const bool degenerate = dl0 == dlk;
-        double W = 0.0, mu = 0.0;
-        for (int q = 0; q < k; ++q) {
-            W += 1.0 / (q + 1);
-            mu += sqrt(sel_d[q]) / (q + 1);
-        }
-        mu /= W;
-        double var = 0.0;
-        for (int q = 0; q < k; ++q) {
-            const double t = sqrt(sel_d[q]) - mu;
-            var += t * t / (q + 1);
-        }
-        var /= W;
-        const bool flat = !(var > 1e-30 * mu * mu);
-        if (lane < k) {
-            const double dq = sqrt(sel_d[lane]);
-            const double ev = flat ? 1.0 : exp((double)a.boost * (mu - dq) / sqrt(var));
-            const double cv = a.use_cutoff ? 1.0 - exp((double)a.cutoff * (dq / dlk - 1.0)) : 1.0;
-            sc[lane] = degenerate ? 0.0 : ev * cv;
+        // 3. scores (wave 0, one neighbour per lane; k <= 64)
+        const bool degenerate = sqrt(sel_d[0]) == sqrt(sel_d[k - 1]);  // all delta equal
+        if (wv == 0) {
+            const double dq = lane < k ? sqrt(sel_d[lane]) : 0.0;
+            const double wq = lane < k ? 1.0 / (lane + 1) : 0.0;
+            const double W = wave_sum(wq);
+            const double mu = wave_sum(wq * dq) / W;
+            const double var = wave_sum(lane < k ? wq * (dq - mu) * (dq - mu) : 0.0) / W;
+            const bool flat = !(var > 1e-30 * mu * mu);
+            if (lane < k) {
+                const double dlk = sqrt(sel_d[k - 1]);
+                const double ev = flat ? 1.0 : exp((double)a.boost * (mu - dq) / sqrt(var));
+                const double cv = a.use_cutoff ? 1.0 - exp((double)a.cutoff * (dq / dlk - 1.0)) : 1.0;
+                sc[lane] = degenerate ? 0.0 : ev * cv;
+            }
         }
         __syncthreads();
-        // pairs spread over the lanes
+        // pairs spread over the threads
         double M00 = 0.0, M01 = 0.0, M11 = 0.0, r0 = 0.0, r1 = 0.0, ssum = 0.0;
         const int npair = k * (k - 1) / 2;
-        for (int p = lane; p < npair && !degenerate; p += 64) {
+        for (int p = tid; p < npair && !degenerate; p += EX_THREADS) {
             int qi = 0, rem = p;
             while (rem >= k - 1 - qi) {
                 rem -= k - 1 - qi;
@@ -253,7 +325,7 @@ __global__ void __launch_bounds__(64) embed_exact(EmbedArgs a, int all_points) {
             const double hx = (double)a.l2d[2 * v] - lux, hy = (double)a.l2d[2 * v + 1] - luy;
             const double hh = hx * hx + hy * hy;
             if (hh == 0.0) continue;
-            const double qw = sc[qi] * sc[qj] * pow(hh, -(double)a.adjust);
+            const double qw = sc[qi] * sc[qj] * (a.adjust == 1.0f ? 1.0 / hh : pow(hh, -(double)a.adjust));
             const double rhs = D + (hx * lux + hy * luy) / hh;
             M00 += qw * hx * hx / hh;
             M01 += qw * hx * hy / hh;
@@ -261,13 +333,13 @@ __global__ void __launch_bounds__(64) embed_exact(EmbedArgs a, int all_points) {
             r0 += qw * hx * rhs;
             r1 += qw * hy * rhs;
         }
-        if (lane < k && !degenerate) {
-            const double gs = (double)a.gravity * sc[lane];
+        if (tid < k && !degenerate) {
+            const double gs = (double)a.gravity * sc[tid];
             M00 += gs;
             M11 += gs;
-            r0 += gs * a.l2d[2 * sel_j[lane]];
-            r1 += gs * a.l2d[2 * sel_j[lane] + 1];
-            ssum += sc[lane];
+            r0 += gs * a.l2d[2 * sel_j[tid]];
+            r1 += gs * a.l2d[2 * sel_j[tid] + 1];
+            ssum += sc[tid];
         }
         M00 = wave_sum(M00);
         M01 = wave_sum(M01);
@@ -276,9 +348,22 @@ __global__ void __launch_bounds__(64) embed_exact(EmbedArgs a, int all_points) {
         r1 = wave_sum(r1);
         ssum = wave_sum(ssum);
         if (lane == 0) {
-            const double det = M00 * M11 - M01 * M01;
+            red[6 * wv + 0] = M00;
+            red[6 * wv + 1] = M01;
+            red[6 * wv + 2] = M11;
+            red[6 * wv + 3] = r0;
+            red[6 * wv + 4] = r1;
+            red[6 * wv + 5] = ssum;
+        }
+        __syncthreads();
+        // 4. solve
+        if (tid == 0) {
+            double t[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
+            for (int w = 0; w < EX_THREADS / 64; ++w)
+                for (int i = 0; i < 6; ++i) t[i] += red[6 * w + i];
+            const double det = t[0] * t[2] - t[1] * t[1];
             double px, py;
-            if (degenerate || !(ssum > 0.0) || !(det > 0.0)) {
+            if (degenerate || !(t[5] > 0.0) || !(det > 0.0)) {
                 double cx = 0.0, cy = 0.0;
                 for (int q = 0; q < k; ++q) {
                     cx += a.l2d[2 * sel_j[q]];
@@ -288,15 +373,15 @@ __global__ void __launch_bounds__(64) embed_exact(EmbedArgs a, int all_points) {
                 py = cy / k;
                 ++n_deg;
             } else {
-                px = (r0 * M11 - M01 * r1) / det;
-                py = (M00 * r1 - M01 * r0) / det;
+                px = (t[3] * t[2] - t[1] * t[4]) / det;
+                py = (t[0] * t[4] - t[1] * t[3]) / det;
             }
             a.out[2 * pi] = (float)px;
             a.out[2 * pi + 1] = (float)py;
         }
         __syncthreads();
     }
-    if (lane == 0 && n_fb) {
+    if (tid == 0 && n_fb) {
         atomicAdd(&a.counters[all_points ? C_SLOW : C_FALLBACK], n_fb);
         if (n_unc) atomicAdd(&a.counters[C_UNCERT], n_unc);
         if (n_tie) atomicAdd(&a.counters[C_NEARTIE], n_tie);
@@ -306,20 +391,21 @@ __global__ void __launch_bounds__(64) embed_exact(EmbedArgs a, int all_points) {
 }
 
 static size_t exact_smem(const EmbedArgs &a) {
-    return sizeof(double) * ((size_t)a.g + a.d + 2 * ESOM_MAX_K + 1) + sizeof(int) * (ESOM_MAX_K + 1);
+    return sizeof(double) * ((size_t)a.g + a.dp + 2 * ESOM_MAX_K + 6 * (EX_THREADS / 64)) +
+           sizeof(int) * (ESOM_MAX_K + EX_SEL_CAP + 2);
 }
 
 hipError_t launch_fallback(const EmbedArgs &a, int num_cus, hipStream_t s) {
     // The list length is only known on the device: a fixed grid loops over it.
-    hipLaunchKernelGGL(embed_exact, dim3(num_cus * 4), dim3(64), exact_smem(a), s, a, 0);
+    hipLaunchKernelGGL(embed_exact, dim3(num_cus * 2), dim3(EX_THREADS), exact_smem(a), s, a, 0);
     return hipGetLastError();
 }
 
 hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, hipStream_t s) {
     long long blocks = a.n;
-    if (blocks > (long long)num_cus * 16) blocks = (long long)num_cus * 16;
+    if (blocks > (long long)num_cus * 8) blocks = (long long)num_cus * 8;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(embed_exact, dim3((unsigned)blocks), dim3(64), exact_smem(a), s, a, 1);
+    hipLaunchKernelGGL(embed_exact, dim3((unsigned)blocks), dim3(EX_THREADS), exact_smem(a), s, a, 1);
     return hipGetLastError();
 }
 

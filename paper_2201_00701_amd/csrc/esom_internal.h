@@ -54,6 +54,7 @@ struct Scratch {
     int64_t cap_n = 0;
     int32_t *fb_list = nullptr;     // fallback point list (cap_n)
     uint8_t *fb_reason = nullptr;   // per listed point reason flags (cap_n)
+    float *fb_thresh = nullptr;     // per listed point: bound of its k-th distance^2 (cap_n)
     unsigned long long *counters = nullptr;  // C_COUNT
     Prep prep;
 };
@@ -72,6 +73,10 @@ struct EmbedArgs {
     float *knn_d2;
     int32_t *fb_list;
     uint8_t *fb_reason;
+    // Per listed point, an upper bound of the exact k-th nearest squared
+    // distance (from the fast kernel's rescored k-th, widened by its rounding
+    // bound), or +inf: the exact path only sorts landmarks within it.
+    float *fb_thresh;
     unsigned long long *counters;
     int knn_only;  // 1: only write knn outputs (no projection)
     int lds_rows;  // 1: the block stages Lpad in LDS (row stride dp + 4 floats)

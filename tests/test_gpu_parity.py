@@ -197,6 +197,23 @@ def test_duplicates_and_degenerate(torch_dev, ctx, oracle_mod):
         np.testing.assert_allclose(out[5], l[40:44].mean(0), atol=1e-6)
 
 
+def test_many_tied_landmarks(torch_dev, ctx, oracle_mod):
+    # 301 identical landmarks (index 0 and 300..599): every point near them has
+    # a k-th/(k+1)-th tie, so the exact path runs with more landmarks within
+    # its distance bound than it ranks by counting (its repeated-minimum branch);
+    # the neighbours must be the lowest tied indices, as in the oracle.
+    X, L, l = _problem(11, 64, 8, 600)
+    L[300:] = L[0]
+    rng = np.random.default_rng(11)
+    X[:32] = L[0] + rng.normal(0, 1e-3, (32, 8)).astype(np.float32)
+    _say("case many tied landmarks g=600 (301 copies)")
+    for mode in ("fp32", "bf16"):
+        out, idx, _ = run_case(torch_dev, ctx, X, L, l, 8, mode)
+        ref = oracle_mod.embed(X, L, l, 8)
+        np.testing.assert_array_equal(idx[:32], ref["idx"][:32, :8])
+        check_parity(X, L, l, 8, out, idx, ref, float(np.ptp(l)), "ties/" + mode)
+
+
 def test_empty_input_is_noop(torch_dev, ctx):
     from paper_2201_00701_amd import esom
     L = torch_dev.zeros((10, 4), device="cuda")

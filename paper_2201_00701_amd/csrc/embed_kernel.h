@@ -158,6 +158,10 @@ struct BoolTag {
 // LDS bytes of the block-wide centroid copy (padded dimension <= 128).
 constexpr int CENT_LDS_BYTES = 512;
 
+// LDS bytes of the block-wide landmark order tables (position -> landmark and
+// landmark -> position, 16-bit each, two halves of equal size).
+__host__ __device__ inline size_t order_lds_bytes(int g) { return (size_t)(((2 * g + 255) / 256) * 256) * 2; }
+
 // Bytes of LDS one wave needs: candidate bitmaps (2 W words per lane), or for
 // KP > 16 the neighbour staging of the pair loop in the same space; then
 // thresholds, norms and the per-lane masks of non-empty bitmap words.
@@ -245,7 +249,8 @@ __device__ __forceinline__ void screen_tile(const EmbedArgs &a, int t, int lane,
 template <int KP>
 __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const double (&sk)[KP],
                                                   int lane, bool valid, long long pi, unsigned reason,
-                                                  float *nbD2, float *nbS, unsigned short *nbI) {
+                                                  float *nbD2, float *nbS, unsigned short *nbI,
+                                                  const unsigned short *iposL) {
     float d2q[KP], dl[KP], sq[KP], lxq[KP], lyq[KP];
     int jq[KP];
     float mu = 0.f;
@@ -339,10 +344,10 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
 #pragma unroll
         for (int qi = 0; qi < KP - 1; ++qi) {
             if (qi < a.kact - 1) {
-                const float *invrow = a.inv2 + (size_t)jq[qi] * a.g;
+                const float *invrow = a.inv2 + (size_t)iposL[jq[qi]] * a.g;
                 float inv[KP];
 #pragma unroll
-                for (int qj = qi + 1; qj < KP; ++qj) inv[qj] = (qj < a.kact) ? invrow[jq[qj]] : -1.f;
+                for (int qj = qi + 1; qj < KP; ++qj) inv[qj] = (qj < a.kact) ? invrow[iposL[jq[qj]]] : -1.f;
 #pragma unroll
                 for (int qj = qi + 1; qj < KP; ++qj)
                     if (qj < a.kact)
@@ -366,7 +371,7 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
             const int ui = nbI[qi * 64 + lane];
             const float2 li = reinterpret_cast<const float2 *>(a.l2d)[ui];
             const float lxi = li.x - ox, lyi = li.y - oy;
-            const float *invrow = a.inv2 + (size_t)ui * a.g;
+            const float *invrow = a.inv2 + (size_t)iposL[ui] * a.g;
             for (int qb = qi + 1; qb < a.kact; qb += 4) {
                 float inv[4], d2j[4], sj[4], lxj[4], lyj[4];
 #pragma unroll
@@ -374,7 +379,7 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
                     const int qj = qb + u;
                     const bool ok = qj < a.kact;
                     const int vj = ok ? nbI[qj * 64 + lane] : 0;
-                    inv[u] = ok ? invrow[vj] : -1.f;
+                    inv[u] = ok ? invrow[iposL[vj]] : -1.f;
                     d2j[u] = ok ? nbD2[qj * 64 + lane] : 0.f;
                     sj[u] = ok ? nbS[qj * 64 + lane] : 0.f;
                     const float2 lv = reinterpret_cast<const float2 *>(a.l2d)[vj];
@@ -420,6 +425,9 @@ __global__ void __launch_bounds__(256) embed_project(EmbedArgs a) {
     float *nbD2 = reinterpret_cast<float *>(wsm);
     float *nbS = nbD2 + KP * 64;
     unsigned short *nbI = reinterpret_cast<unsigned short *>(nbS + KP * 64);
+    unsigned short *iposL = reinterpret_cast<unsigned short *>(smem + (size_t)wpb * (KP * 64 * 10));
+    for (int e = threadIdx.x; e < a.g; e += blockDim.x) iposL[e] = (unsigned short)a.ipos[e];
+    __syncthreads();
     const int64_t nwt = (a.n + 63) / 64;
     for (int64_t wt = (int64_t)blockIdx.x * wpb + wave; wt < nwt; wt += (int64_t)gridDim.x * wpb) {
         const int64_t pi = wt * 64 + lane;
@@ -437,7 +445,7 @@ __global__ void __launch_bounds__(256) embed_project(EmbedArgs a) {
         for (int q = 0; q < KP; ++q)
             if (q == a.k - 1) d2k = key_d2(sk[q]);
         const float thr = kth_bound(d2k, a.dp);
-        reason = project_point<KP>(a, sk, lane, valid, pi, reason, nbD2, nbS, nbI);
+        reason = project_point<KP>(a, sk, lane, valid, pi, reason, nbD2, nbS, nbI, iposL);
         if (valid && reason) {
             const unsigned long long slot = atomicAdd(&a.counters[C_FB_LEN], 1ull);
             a.fb_list[slot] = (int32_t)pi;
@@ -461,9 +469,16 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
     // Block-wide copies: the centroid (read for every point group), and
     // optionally the landmark rows for exact rescoring.
     float *centL = reinterpret_cast<float *>(smem);
-    float *rowsL = reinterpret_cast<float *>(smem + CENT_LDS_BYTES);
+    const size_t tab_bytes = order_lds_bytes(a.g);
+    unsigned short *permL = reinterpret_cast<unsigned short *>(smem + CENT_LDS_BYTES);
+    unsigned short *iposL = permL + tab_bytes / 4;
+    float *rowsL = reinterpret_cast<float *>(smem + CENT_LDS_BYTES + tab_bytes);
     const size_t rows_bytes = a.lds_rows ? (((size_t)a.g * RS * 4 + 255) & ~(size_t)255) : 0;
     for (int e = threadIdx.x; e < DP; e += blockDim.x) centL[e] = e < a.d ? a.cent[e] : 0.f;
+    for (int e = threadIdx.x; e < a.g; e += blockDim.x) {
+        permL[e] = (unsigned short)a.perm[e];
+        iposL[e] = (unsigned short)a.ipos[e];
+    }
     if (a.lds_rows) {
         for (int e = threadIdx.x; e < a.g * (DP / 4); e += blockDim.x) {
             const int j = e / (DP / 4), q = e % (DP / 4);
@@ -472,7 +487,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         }
     }
     __syncthreads();
-    unsigned char *wsm = smem + CENT_LDS_BYTES + rows_bytes + (size_t)wave * wave_smem_bytes(KP, W);
+    unsigned char *wsm = smem + CENT_LDS_BYTES + tab_bytes + rows_bytes + (size_t)wave * wave_smem_bytes(KP, W);
     unsigned *bitsL = reinterpret_cast<unsigned *>(wsm);
     float *nbD2 = reinterpret_cast<float *>(wsm);
     float *nbS = nbD2 + KP * 64;
@@ -724,7 +739,8 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                         acc = fmaf(e3, e3, acc);
                     }
                 }
-                insert_sorted<KP>(sk, rej, act ? pack_key(acc, j) : (double)INFINITY);
+                // keys carry the landmark index (ties break on it), not the position
+                insert_sorted<KP>(sk, rej, act ? pack_key(acc, permL[j]) : (double)INFINITY);
                 m += act ? 1 : 0;
             }
         }
@@ -768,7 +784,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
 
         if (!a.knn_only) {
             __builtin_amdgcn_wave_barrier();
-            reason = project_point<KP>(a, sk, lane, valid, pi, reason, nbD2, nbS, nbI);
+            reason = project_point<KP>(a, sk, lane, valid, pi, reason, nbD2, nbS, nbI, iposL);
         }
         if (valid && reason) {
             const unsigned long long slot = atomicAdd(&a.counters[C_FB_LEN], 1ull);

@@ -94,6 +94,10 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp) {
     sc.prep.Lpad = static_cast<float *>(take(sizeof(float) * (size_t)g * dp));
     sc.prep.inv2 = static_cast<float *>(take(sizeof(float) * (size_t)g * g));
     sc.prep.lmax = static_cast<float *>(take(sizeof(float)));
+    sc.prep.perm = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
+    sc.prep.ipos = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
+    sc.prep.pcl = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
+    sc.prep.pdist = static_cast<float *>(take(sizeof(float) * (size_t)g));
     sc.fb_list = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     sc.fb_reason = static_cast<uint8_t *>(take((size_t)(n > 0 ? n : 1)));
     sc.fb_thresh = static_cast<float *>(take(sizeof(float) * (size_t)(n > 0 ? n : 1)));
@@ -216,6 +220,8 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
     a.l2d = l2d;
     a.inv2 = pr.inv2;
     a.lmax = pr.lmax;
+    a.perm = pr.perm;
+    a.ipos = pr.ipos;
     a.k = P.k;
     a.kact = P.k < g ? P.k - 1 : P.k;
     a.jsel = pl.jsel;

@@ -11,13 +11,62 @@ namespace esom {
 
 // ---------------------------------------------------------------- preparation
 
+// Landmark order.  The screen tiles, the rescoring rows and the pair table
+// hold the landmarks in an order where landmarks close in the input space
+// get nearby positions: a point's candidates then fill fewer bitmap words,
+// and the pair-table entries of its neighbours share cache lines.  The
+// order: P = min(64, g) pivots (landmarks floor(i g / P)); each landmark
+// joins its nearest pivot; the pivots are chained greedily from pivot 0 (each
+// next pivot the nearest one not yet taken); landmarks are sorted by (their
+// pivot's place in the chain, distance to the pivot, index).  Only speed
+// depends on it: results follow the landmark indices, which the keys carry.
+constexpr int ORDER_MAX_P = 64;
+
+__host__ __device__ inline int order_pivots(int g) { return g < ORDER_MAX_P ? g : ORDER_MAX_P; }
+
 // Centroid of the landmarks (FP64 sum, rounded to FP32), zero-padded to dp:
-// one block per dimension.  Block 0 also resets the per-call fallback list
-// and the landmark norm maximum, and counts the points of this call.
+// blocks 0 .. dp-1, one per dimension.  Block 0 also resets the per-call
+// fallback list and the landmark norm maximum, and counts the points of this
+// call.  Blocks dp .. : one wavefront per landmark, lanes over the pivots:
+// nearest pivot (squared FP32 distance, ties to the lower pivot) into
+// pcl[j] and that distance into pdist[j].
 __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
                               float *__restrict__ cent, float *__restrict__ lmax,
-                              unsigned long long *__restrict__ counters, long long n_points) {
+                              unsigned long long *__restrict__ counters, long long n_points,
+                              int *__restrict__ pcl, float *__restrict__ pdist) {
     __shared__ double red[256];
+    if ((int)blockIdx.x >= dp) {
+        const int j = ((int)blockIdx.x - dp) * (blockDim.x / 64) + (threadIdx.x >> 6);
+        const int lane = threadIdx.x & 63;
+        if (j >= g) return;
+        const int P = order_pivots(g);
+        float dd = INFINITY;
+        if (lane < P) {
+            const int pv = (int)(((long long)lane * g) / P);
+            const float *Lj = L + (size_t)j * d, *Lp = L + (size_t)pv * d;
+            float s = 0.f;
+            for (int q = 0; q < d; ++q) {
+                const float df = Lj[q] - Lp[q];
+                s = fmaf(df, df, s);
+            }
+            dd = s;
+        }
+        int bi = lane < P ? lane : 0x7fffffff;
+#pragma unroll
+        for (int o = 32; o > 0; o >>= 1) {
+            const float od = __shfl_xor(dd, o);
+            const int oi = __shfl_xor(bi, o);
+            if (od < dd || (od == dd && oi < bi)) {
+                dd = od;
+                bi = oi;
+            }
+        }
+        if (lane == 0) {
+            pcl[j] = bi == 0x7fffffff ? 0 : bi;
+            pdist[j] = dd;
+        }
+        return;
+    }
     const int t = blockIdx.x;
     double s = 0.0;
     if (t < d)
@@ -36,22 +85,108 @@ __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
     }
 }
 
+// One block: the pivot chain and the sort of the landmarks by (chain place
+// of their pivot, distance to it, index), as 64-bit keys in an LDS bitonic
+// sort.  Writes perm (position -> landmark) and ipos (landmark -> position).
+__global__ void __launch_bounds__(1024) prep_order(const float *__restrict__ L, int g, int d,
+                                                   const int *__restrict__ pcl,
+                                                   const float *__restrict__ pdist,
+                                                   int *__restrict__ perm, int *__restrict__ ipos) {
+    extern __shared__ __align__(16) unsigned char osm[];
+    const int P = order_pivots(g);
+    int gp2 = 1;
+    while (gp2 < g) gp2 <<= 1;
+    unsigned long long *key = reinterpret_cast<unsigned long long *>(osm);  // gp2
+    float *pp = reinterpret_cast<float *>(key + gp2);                        // P x P
+    int *place = reinterpret_cast<int *>(pp + ORDER_MAX_P * ORDER_MAX_P);   // P
+    const int tid = threadIdx.x;
+    // pivot-to-pivot squared distances
+    for (int e = tid; e < P * P; e += blockDim.x) {
+        const int a = e / P, b = e % P;
+        const float *La = L + (size_t)(((long long)a * g) / P) * d;
+        const float *Lb = L + (size_t)(((long long)b * g) / P) * d;
+        float s = 0.f;
+        for (int q = 0; q < d; ++q) {
+            const float df = La[q] - Lb[q];
+            s = fmaf(df, df, s);
+        }
+        pp[e] = s;
+    }
+    __syncthreads();
+    // greedy chain over the pivots (one wavefront, lane = pivot)
+    if (tid < 64) {
+        bool taken = tid == 0;
+        int cur = 0;
+        if (tid == 0) place[0] = 0;
+        for (int r = 1; r < P; ++r) {
+            float dd = (tid < P && !taken) ? pp[cur * P + tid] : INFINITY;
+            int bi = (tid < P && !taken) ? tid : 0x7fffffff;
+#pragma unroll
+            for (int o = 32; o > 0; o >>= 1) {
+                const float od = __shfl_xor(dd, o);
+                const int oi = __shfl_xor(bi, o);
+                if (od < dd || (od == dd && oi < bi)) {
+                    dd = od;
+                    bi = oi;
+                }
+            }
+            cur = bi;
+            if (tid == cur) taken = true;
+            if (tid == 0) place[cur] = r;
+        }
+    }
+    __syncthreads();
+    // keys: place (6 bits) | distance bits (31) | index (13); padding sorts last
+    for (int j = tid; j < gp2; j += blockDim.x) {
+        unsigned long long kv = ~0ull;
+        if (j < g) {
+            const unsigned db = __float_as_uint(fmaxf(pdist[j], 0.f)) & 0x7fffffffu;
+            kv = ((unsigned long long)place[pcl[j]] << 44) | ((unsigned long long)db << 13) |
+                 (unsigned long long)j;
+        }
+        key[j] = kv;
+    }
+    __syncthreads();
+    for (int k = 2; k <= gp2; k <<= 1) {
+        for (int jj = k >> 1; jj > 0; jj >>= 1) {
+            for (int i = tid; i < gp2; i += blockDim.x) {
+                const int l = i ^ jj;
+                if (l > i) {
+                    const unsigned long long x = key[i], y = key[l];
+                    const bool up = (i & k) == 0;
+                    if ((x > y) == up) {
+                        key[i] = y;
+                        key[l] = x;
+                    }
+                }
+            }
+            __syncthreads();
+        }
+    }
+    for (int pos = tid; pos < g; pos += blockDim.x) {
+        const int j = (int)(key[pos] & 0x1FFFull);
+        perm[pos] = j;
+        ipos[j] = pos;
+    }
+}
+
 // One wavefront per (padded) landmark, lanes over dimensions: centred row,
 // squared norm (FP64 wave sum), MFMA operand entries, the zero-padded FP32
 // copy for exact rescoring, and the norm maximum.
-__global__ void prep_landmarks(const float *__restrict__ L, int g, int gpad, int d, int dp,
-                               int mode, const float *__restrict__ cent, void *__restrict__ A,
-                               float *__restrict__ norms, float *__restrict__ Lpad,
-                               float *__restrict__ lmax) {
+__global__ void prep_landmarks(const float *__restrict__ L, const int *__restrict__ perm, int g,
+                               int gpad, int d, int dp, int mode, const float *__restrict__ cent,
+                               void *__restrict__ A, float *__restrict__ norms,
+                               float *__restrict__ Lpad, float *__restrict__ lmax) {
     const int j = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (j >= gpad) return;
     const int t = j / TILE, m = j % TILE;
     const int dc = dp / 16;
     const bool real = j < g;
+    const size_t src = real ? (size_t)perm[j] * d : 0;
     double nrm = 0.0;
     for (int q = lane; q < dp; q += 64) {
-        const float lv = (real && q < d) ? L[(size_t)j * d + q] : 0.f;
+        const float lv = (real && q < d) ? L[src + q] : 0.f;
         const float c = (real && q < d) ? lv - cent[q] : 0.f;
         nrm += (double)c * (double)c;
         if (real) Lpad[(size_t)j * dp + q] = lv;
@@ -81,13 +216,14 @@ __global__ void prep_landmarks(const float *__restrict__ L, int g, int gpad, int
 }
 
 // Pair table inv2[u][v] = 1 / (2 |L_u - L_v|^2) (FP64 differences), -1 when
-// zero.  A 256-thread block computes a 16 x 16 tile of pairs from the two
+// zero, indexed by landmark positions.  A 256-thread block computes a 16 x 16 tile of pairs from the two
 // 16-row slices of L staged in LDS (row stride d + 1 floats: no bank
 // conflicts between the 16 rows a wave reads); rows are read and the table
 // written coalesced.
 constexpr int PAIR_TILE = 16;
 
-__global__ void __launch_bounds__(256) prep_pairs(const float *__restrict__ L, int g, int d,
+__global__ void __launch_bounds__(256) prep_pairs(const float *__restrict__ L,
+                                                  const int *__restrict__ perm, int g, int d,
                                                   float *__restrict__ inv2) {
     extern __shared__ float prs[];  // 2 x PAIR_TILE x (d + 1)
     const int ntu = (g + PAIR_TILE - 1) / PAIR_TILE;
@@ -96,8 +232,8 @@ __global__ void __launch_bounds__(256) prep_pairs(const float *__restrict__ L, i
     float *Lu = prs, *Lv = prs + PAIR_TILE * rs;
     for (int e = threadIdx.x; e < PAIR_TILE * d; e += blockDim.x) {
         const int r = e / d, q = e % d;
-        Lu[r * rs + q] = u0 + r < g ? L[(size_t)(u0 + r) * d + q] : 0.f;
-        Lv[r * rs + q] = v0 + r < g ? L[(size_t)(v0 + r) * d + q] : 0.f;
+        Lu[r * rs + q] = u0 + r < g ? L[(size_t)perm[u0 + r] * d + q] : 0.f;
+        Lv[r * rs + q] = v0 + r < g ? L[(size_t)perm[v0 + r] * d + q] : 0.f;
     }
     __syncthreads();
     const int ty = threadIdx.x / PAIR_TILE, tx = threadIdx.x % PAIR_TILE;
@@ -113,31 +249,24 @@ __global__ void __launch_bounds__(256) prep_pairs(const float *__restrict__ L, i
 
 hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long long *counters,
                        long long n_points, hipStream_t s) {
-    hipLaunchKernelGGL(prep_centroid, dim3(P.dp), dim3(256), 0, s, L, P.g, P.d, P.dp, P.cent,
-                       P.lmax, counters, n_points);
+    hipLaunchKernelGGL(prep_centroid, dim3(P.dp + (P.g + 3) / 4), dim3(256), 0, s, L, P.g, P.d, P.dp,
+                       P.cent, P.lmax, counters, n_points, P.pcl, P.pdist);
+    int gp2 = 1;
+    while (gp2 < P.g) gp2 <<= 1;
+    const size_t osm = sizeof(unsigned long long) * gp2 + sizeof(float) * ORDER_MAX_P * ORDER_MAX_P +
+                       sizeof(int) * ORDER_MAX_P;
+    hipLaunchKernelGGL(prep_order, dim3(1), dim3(1024), osm, s, L, P.g, P.d, P.pcl, P.pdist, P.perm,
+                       P.ipos);
     const int gpad = P.ntiles * TILE;
-    hipLaunchKernelGGL(prep_landmarks, dim3((gpad + 3) / 4), dim3(256), 0, s, L, P.g, gpad, P.d,
-                       P.dp, mode, P.cent, P.A, P.norms, P.Lpad, P.lmax);
+    hipLaunchKernelGGL(prep_landmarks, dim3((gpad + 3) / 4), dim3(256), 0, s, L, P.perm, P.g, gpad,
+                       P.d, P.dp, mode, P.cent, P.A, P.norms, P.Lpad, P.lmax);
     const int ntu = (P.g + PAIR_TILE - 1) / PAIR_TILE;
     hipLaunchKernelGGL(prep_pairs, dim3((unsigned)(ntu * ntu)), dim3(256),
-                       sizeof(float) * 2 * PAIR_TILE * (P.d + 1), s, L, P.g, P.d, P.inv2);
+                       sizeof(float) * 2 * PAIR_TILE * (P.d + 1), s, L, P.perm, P.g, P.d, P.inv2);
     return hipGetLastError();
 }
 
 // ---------------------------------------------------------------- exact FP64 path
-
-// (distance, index) lexicographic minimum across the wavefront.
-__device__ __forceinline__ void wave_argmin(double &v, int &j) {
-#pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        const double ov = __shfl_xor(v, o);
-        const int oj = __shfl_xor(j, o);
-        if (ov < v || (ov == v && oj < j)) {
-            v = ov;
-            j = oj;
-        }
-    }
-}
 
 __device__ __forceinline__ double wave_sum(double v) {
 #pragma unroll
@@ -173,8 +302,9 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
     double *sc = sel_d + ESOM_MAX_K;                        // k
     double *red = sc + ESOM_MAX_K;                          // 6 per wave
     int *sel_j = reinterpret_cast<int *>(red + 6 * (EX_THREADS / 64));  // k
-    int *cand = sel_j + ESOM_MAX_K;                         // EX_SEL_CAP
-    int *flags = cand + EX_SEL_CAP;                         // [0] count, [1] bad
+    int *cand = sel_j + ESOM_MAX_K;                         // EX_SEL_CAP positions
+    int *cando = cand + EX_SEL_CAP;                         // EX_SEL_CAP landmark indices
+    int *flags = cando + EX_SEL_CAP;                        // [0] count, [1] bad
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
@@ -199,7 +329,8 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
             flags[1] = 0;
         }
         __syncthreads();
-        // 1. distances; collect the landmarks within the bound
+        // 1. distances (LDS and rows by landmark position); collect the
+        // landmarks within the bound
         for (int j = tid; j < g; j += EX_THREADS) {
             const float4 *Lj = reinterpret_cast<const float4 *>(a.Lpad + (size_t)j * a.dp);
             double s = 0.0;
@@ -215,7 +346,10 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
             dist[j] = s;
             if (s <= thr) {
                 const int slot = atomicAdd(&flags[0], 1);
-                if (slot < EX_SEL_CAP) cand[slot] = j;
+                if (slot < EX_SEL_CAP) {
+                    cand[slot] = j;
+                    cando[slot] = a.perm[j];
+                }
             }
         }
         __syncthreads();
@@ -223,13 +357,10 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
         const int nc = flags[0];
         if (nc >= k && nc <= EX_SEL_CAP) {
             for (int c = tid; c < nc; c += EX_THREADS) {
-                const int jc = cand[c];
-                const double dc = dist[jc];
+                const double dc = dist[cand[c]];
+                const int jc = cando[c];
                 int rank = 0;
-                for (int o = 0; o < nc; ++o) {
-                    const int jo = cand[o];
-                    rank += lex_less(dist[jo], jo, dc, jc) ? 1 : 0;
-                }
+                for (int o = 0; o < nc; ++o) rank += lex_less(dist[cand[o]], cando[o], dc, jc) ? 1 : 0;
                 if (rank < k) {
                     sel_d[rank] = dc;
                     sel_j[rank] = jc;
@@ -239,20 +370,31 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
             // k repeated minima over all g; taken entries become NaN (never minimal)
             for (int r = 0; r < k; ++r) {
                 double bv = INFINITY;
-                int bj = 0x7fffffff;
+                int bj = 0x7fffffff, bp = 0;  // landmark index, its position
                 for (int j = lane; j < g; j += 64) {
                     const double v = dist[j];
-                    if (v < bv || (v == bv && j < bj)) {
+                    const int o = a.perm[j];
+                    if (v < bv || (v == bv && o < bj)) {
                         bv = v;
-                        bj = j;
+                        bj = o;
+                        bp = j;
                     }
                 }
-                wave_argmin(bv, bj);
+#pragma unroll
+                for (int off = 32; off > 0; off >>= 1) {
+                    const double ov = __shfl_xor(bv, off);
+                    const int oj = __shfl_xor(bj, off), op = __shfl_xor(bp, off);
+                    if (ov < bv || (ov == bv && oj < bj)) {
+                        bv = ov;
+                        bj = oj;
+                        bp = op;
+                    }
+                }
                 if (lane == 0) {
                     sel_d[r] = bv;
                     sel_j[r] = bj;
                     if (bj != 0x7fffffff)
-                        dist[bj] = NAN;
+                        dist[bp] = NAN;
                     else
                         flags[1] = 1;
                 }
@@ -311,8 +453,8 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
             }
             const int qj = qi + 1 + rem;
             const int u = sel_j[qi], v = sel_j[qj];
-            const float *Lu = a.Lpad + (size_t)u * a.dp;
-            const float *Lv = a.Lpad + (size_t)v * a.dp;
+            const float *Lu = a.Lpad + (size_t)a.ipos[u] * a.dp;
+            const float *Lv = a.Lpad + (size_t)a.ipos[v] * a.dp;
             double HH = 0.0, xH = 0.0;
             for (int q = 0; q < a.d; ++q) {
                 const double H = (double)Lv[q] - (double)Lu[q];
@@ -392,7 +534,7 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
 
 static size_t exact_smem(const EmbedArgs &a) {
     return sizeof(double) * ((size_t)a.g + a.dp + 2 * ESOM_MAX_K + 6 * (EX_THREADS / 64)) +
-           sizeof(int) * (ESOM_MAX_K + EX_SEL_CAP + 2);
+           sizeof(int) * (ESOM_MAX_K + 2 * EX_SEL_CAP + 2);
 }
 
 hipError_t launch_fallback(const EmbedArgs &a, int num_cus, hipStream_t s) {
@@ -413,7 +555,7 @@ hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, hipStream_t s
 
 hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s) {
     const int block = 256, wpb = 4;
-    const size_t smem = (size_t)wpb * kp * 64 * 10;
+    const size_t smem = (size_t)wpb * kp * 64 * 10 + sizeof(unsigned short) * (size_t)a.g;
     long long blocks = ((a.n + 63) / 64 + wpb - 1) / wpb;
     if (blocks > (long long)num_cus * 8) blocks = (long long)num_cus * 8;
     if (blocks < 1) blocks = 1;
@@ -450,16 +592,17 @@ hipError_t launch_embed(const EmbedArgs &a0, int mode, int kp, int num_cus, size
     // per CU.
     const int max_wpb = main_max_block(mode, dc, kp) / 64;
     int wpb;
-    if (CENT_LDS_BYTES + rows + (size_t)max_wpb * wsm <= lds_per_block) {
+    const size_t fixed = CENT_LDS_BYTES + order_lds_bytes(a.g);
+    if (fixed + rows + (size_t)max_wpb * wsm <= lds_per_block) {
         a.lds_rows = 1;
         wpb = max_wpb;
     } else {
         a.lds_rows = 0;
-        wpb = (int)((lds_per_block - CENT_LDS_BYTES) / wsm);
+        wpb = (int)((lds_per_block - fixed) / wsm);
         if (wpb > 4) wpb = 4;
         if (wpb < 1) wpb = 1;
     }
-    const size_t smem = CENT_LDS_BYTES + (a.lds_rows ? rows : 0) + (size_t)wpb * wsm;
+    const size_t smem = fixed + (a.lds_rows ? rows : 0) + (size_t)wpb * wsm;
     const int block = 64 * wpb;
     if (mode == 0) {
         if (kp == 8) return launch_main_m0_kp8(a, dc, block, smem, num_cus, s);

@@ -45,6 +45,13 @@ struct Prep {
     float *Lpad = nullptr;   // g * dp:  L rows padded with zeros to dp
     float *inv2 = nullptr;   // g * g:   1 / (2 |L_u - L_v|^2), -1 if zero
     float *lmax = nullptr;   // 1:       max_j |L_j - c|
+    // Landmark order of the screen tiles, rows and pair table: position ->
+    // landmark (perm) and landmark -> position (ipos).  Landmarks that are
+    // close in the input space get nearby positions (see prep_order).
+    int32_t *perm = nullptr;  // g
+    int32_t *ipos = nullptr;  // g
+    int32_t *pcl = nullptr;   // g: nearest ordering pivot (preparation scratch)
+    float *pdist = nullptr;   // g: squared distance to it (preparation scratch)
 };
 
 // Scratch memory for one in-flight embed (grows on demand).
@@ -65,6 +72,7 @@ struct EmbedArgs {
     int d, dp, g, ntiles, npair_tiles;
     const void *A;
     const float *norms, *cent, *Lpad, *l2d, *inv2, *lmax;
+    const int32_t *perm, *ipos;  // position -> landmark, landmark -> position
     int k, kact, jsel;  // kact: neighbours with non-zero score; jsel: per-lane order statistic
     int use_cutoff;
     float boost, cutoff, gravity, adjust, Wk;

@@ -98,6 +98,7 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp) {
     sc.prep.ipos = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
     sc.prep.pcl = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
     sc.prep.pdist = static_cast<float *>(take(sizeof(float) * (size_t)g));
+    sc.prep.ppiv = static_cast<float *>(take(sizeof(float) * 64 * 64));
     sc.fb_list = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     sc.fb_reason = static_cast<uint8_t *>(take((size_t)(n > 0 ? n : 1)));
     sc.fb_thresh = static_cast<float *>(take(sizeof(float) * (size_t)(n > 0 ? n : 1)));

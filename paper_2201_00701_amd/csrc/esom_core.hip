@@ -22,6 +22,9 @@ namespace esom {
 // depends on it: results follow the landmark indices, which the keys carry.
 constexpr int ORDER_MAX_P = 64;
 
+// Wavefront minimum of an unsigned value (device library, DPP reduction).
+extern "C" __device__ unsigned int __ockl_wfred_min_u32(unsigned int);
+
 __host__ __device__ inline int order_pivots(int g) { return g < ORDER_MAX_P ? g : ORDER_MAX_P; }
 
 // Centroid of the landmarks (FP64 sum, rounded to FP32), zero-padded to dp:
@@ -29,11 +32,13 @@ __host__ __device__ inline int order_pivots(int g) { return g < ORDER_MAX_P ? g 
 // fallback list and the landmark norm maximum, and counts the points of this
 // call.  Blocks dp .. : one wavefront per landmark, lanes over the pivots:
 // nearest pivot (squared FP32 distance, ties to the lower pivot) into
-// pcl[j] and that distance into pdist[j].
+// pcl[j] and that distance into pdist[j]; a pivot's wavefront also writes
+// its row of pivot-to-pivot distances into pp.
 __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
                               float *__restrict__ cent, float *__restrict__ lmax,
                               unsigned long long *__restrict__ counters, long long n_points,
-                              int *__restrict__ pcl, float *__restrict__ pdist) {
+                              int *__restrict__ pcl, float *__restrict__ pdist,
+                              float *__restrict__ pp) {
     __shared__ double red[256];
     if ((int)blockIdx.x >= dp) {
         const int j = ((int)blockIdx.x - dp) * (blockDim.x / 64) + (threadIdx.x >> 6);
@@ -50,6 +55,10 @@ __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
                 s = fmaf(df, df, s);
             }
             dd = s;
+        }
+        {
+            const int pi = (int)(((long long)j * P + g - 1) / g);  // the pivot j may be
+            if (pi < P && (int)(((long long)pi * g) / P) == j && lane < P) pp[pi * P + lane] = dd;
         }
         int bi = lane < P ? lane : 0x7fffffff;
 #pragma unroll
@@ -85,86 +94,52 @@ __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
     }
 }
 
-// One block: the pivot chain and the sort of the landmarks by (chain place
-// of their pivot, distance to it, index), as 64-bit keys in an LDS bitonic
-// sort.  Writes perm (position -> landmark) and ipos (landmark -> position).
-__global__ void __launch_bounds__(1024) prep_order(const float *__restrict__ L, int g, int d,
-                                                   const int *__restrict__ pcl,
+// One block: the pivot chain, then the landmarks ranked by (chain place of
+// their pivot, distance to it, index) as 64-bit keys (each thread counts the
+// smaller keys of its landmark).  Writes perm (position -> landmark) and ipos
+// (landmark -> position).
+__global__ void __launch_bounds__(1024) prep_order(int g, const int *__restrict__ pcl,
                                                    const float *__restrict__ pdist,
+                                                   const float *__restrict__ ppg,
                                                    int *__restrict__ perm, int *__restrict__ ipos) {
     extern __shared__ __align__(16) unsigned char osm[];
     const int P = order_pivots(g);
-    int gp2 = 1;
-    while (gp2 < g) gp2 <<= 1;
-    unsigned long long *key = reinterpret_cast<unsigned long long *>(osm);  // gp2
-    float *pp = reinterpret_cast<float *>(key + gp2);                        // P x P
+    unsigned long long *key = reinterpret_cast<unsigned long long *>(osm);  // g
+    float *pp = reinterpret_cast<float *>(key + g);                          // P x P
     int *place = reinterpret_cast<int *>(pp + ORDER_MAX_P * ORDER_MAX_P);   // P
     const int tid = threadIdx.x;
-    // pivot-to-pivot squared distances
-    for (int e = tid; e < P * P; e += blockDim.x) {
-        const int a = e / P, b = e % P;
-        const float *La = L + (size_t)(((long long)a * g) / P) * d;
-        const float *Lb = L + (size_t)(((long long)b * g) / P) * d;
-        float s = 0.f;
-        for (int q = 0; q < d; ++q) {
-            const float df = La[q] - Lb[q];
-            s = fmaf(df, df, s);
-        }
-        pp[e] = s;
-    }
+    // pivot-to-pivot squared distances (from the assignment pass)
+    for (int e = tid; e < P * P; e += blockDim.x) pp[e] = ppg[e];
     __syncthreads();
-    // greedy chain over the pivots (one wavefront, lane = pivot)
+    // greedy chain over the pivots (one wavefront, lane = pivot): each step
+    // takes the nearest pivot not yet taken, by a wave minimum of 32-bit keys
+    // (distance bits with the 6 low bits replaced by the pivot number)
     if (tid < 64) {
         bool taken = tid == 0;
         int cur = 0;
         if (tid == 0) place[0] = 0;
         for (int r = 1; r < P; ++r) {
-            float dd = (tid < P && !taken) ? pp[cur * P + tid] : INFINITY;
-            int bi = (tid < P && !taken) ? tid : 0x7fffffff;
-#pragma unroll
-            for (int o = 32; o > 0; o >>= 1) {
-                const float od = __shfl_xor(dd, o);
-                const int oi = __shfl_xor(bi, o);
-                if (od < dd || (od == dd && oi < bi)) {
-                    dd = od;
-                    bi = oi;
-                }
-            }
-            cur = bi;
+            unsigned kv = 0xffffffffu;
+            if (tid < P && !taken) kv = (__float_as_uint(fmaxf(pp[cur * P + tid], 0.f)) & ~63u) | (unsigned)tid;
+            cur = (int)(__ockl_wfred_min_u32(kv) & 63u);
             if (tid == cur) taken = true;
             if (tid == 0) place[cur] = r;
         }
     }
     __syncthreads();
-    // keys: place (6 bits) | distance bits (31) | index (13); padding sorts last
-    for (int j = tid; j < gp2; j += blockDim.x) {
-        unsigned long long kv = ~0ull;
-        if (j < g) {
-            const unsigned db = __float_as_uint(fmaxf(pdist[j], 0.f)) & 0x7fffffffu;
-            kv = ((unsigned long long)place[pcl[j]] << 44) | ((unsigned long long)db << 13) |
+    // keys: place (6 bits) | distance bits (31) | index (13)
+    for (int j = tid; j < g; j += blockDim.x) {
+        const unsigned db = __float_as_uint(fmaxf(pdist[j], 0.f)) & 0x7fffffffu;
+        key[j] = ((unsigned long long)place[pcl[j]] << 44) | ((unsigned long long)db << 13) |
                  (unsigned long long)j;
-        }
-        key[j] = kv;
     }
     __syncthreads();
-    for (int k = 2; k <= gp2; k <<= 1) {
-        for (int jj = k >> 1; jj > 0; jj >>= 1) {
-            for (int i = tid; i < gp2; i += blockDim.x) {
-                const int l = i ^ jj;
-                if (l > i) {
-                    const unsigned long long x = key[i], y = key[l];
-                    const bool up = (i & k) == 0;
-                    if ((x > y) == up) {
-                        key[i] = y;
-                        key[l] = x;
-                    }
-                }
-            }
-            __syncthreads();
-        }
-    }
-    for (int pos = tid; pos < g; pos += blockDim.x) {
-        const int j = (int)(key[pos] & 0x1FFFull);
+    // position of each landmark = number of smaller keys (keys are distinct)
+    for (int j = tid; j < g; j += blockDim.x) {
+        const unsigned long long kj = key[j];
+        int pos = 0;
+#pragma unroll 8
+        for (int i = 0; i < g; ++i) pos += key[i] < kj ? 1 : 0;
         perm[pos] = j;
         ipos[j] = pos;
     }
@@ -250,12 +225,10 @@ __global__ void __launch_bounds__(256) prep_pairs(const float *__restrict__ L,
 hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long long *counters,
                        long long n_points, hipStream_t s) {
     hipLaunchKernelGGL(prep_centroid, dim3(P.dp + (P.g + 3) / 4), dim3(256), 0, s, L, P.g, P.d, P.dp,
-                       P.cent, P.lmax, counters, n_points, P.pcl, P.pdist);
-    int gp2 = 1;
-    while (gp2 < P.g) gp2 <<= 1;
-    const size_t osm = sizeof(unsigned long long) * gp2 + sizeof(float) * ORDER_MAX_P * ORDER_MAX_P +
+                       P.cent, P.lmax, counters, n_points, P.pcl, P.pdist, P.ppiv);
+    const size_t osm = sizeof(unsigned long long) * P.g + sizeof(float) * ORDER_MAX_P * ORDER_MAX_P +
                        sizeof(int) * ORDER_MAX_P;
-    hipLaunchKernelGGL(prep_order, dim3(1), dim3(1024), osm, s, L, P.g, P.d, P.pcl, P.pdist, P.perm,
+    hipLaunchKernelGGL(prep_order, dim3(1), dim3(1024), osm, s, P.g, P.pcl, P.pdist, P.ppiv, P.perm,
                        P.ipos);
     const int gpad = P.ntiles * TILE;
     hipLaunchKernelGGL(prep_landmarks, dim3((gpad + 3) / 4), dim3(256), 0, s, L, P.perm, P.g, gpad,

@@ -52,6 +52,7 @@ struct Prep {
     int32_t *ipos = nullptr;  // g
     int32_t *pcl = nullptr;   // g: nearest ordering pivot (preparation scratch)
     float *pdist = nullptr;   // g: squared distance to it (preparation scratch)
+    float *ppiv = nullptr;    // 64 x 64: pivot-to-pivot squared distances (scratch)
 };
 
 // Scratch memory for one in-flight embed (grows on demand).

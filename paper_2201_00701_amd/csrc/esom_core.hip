@@ -21,6 +21,7 @@ namespace esom {
 // pivot's place in the chain, distance to the pivot, index).  Only speed
 // depends on it: results follow the landmark indices, which the keys carry.
 constexpr int ORDER_MAX_P = 64;
+constexpr int ASSIGN_PER_BLOCK = 16;  // landmarks per assignment block
 
 // Wavefront minimum of an unsigned value (device library, DPP reduction).
 extern "C" __device__ unsigned int __ockl_wfred_min_u32(unsigned int);
@@ -30,10 +31,10 @@ __host__ __device__ inline int order_pivots(int g) { return g < ORDER_MAX_P ? g 
 // Centroid of the landmarks (FP64 sum, rounded to FP32), zero-padded to dp:
 // blocks 0 .. dp-1, one per dimension.  Block 0 also resets the per-call
 // fallback list and the landmark norm maximum, and counts the points of this
-// call.  Blocks dp .. : one wavefront per landmark, lanes over the pivots:
-// nearest pivot (squared FP32 distance, ties to the lower pivot) into
-// pcl[j] and that distance into pdist[j]; a pivot's wavefront also writes
-// its row of pivot-to-pivot distances into pp.
+// call.  Blocks dp .. : the landmarks' nearest pivots (squared FP32
+// distance; equal leading bits break to the lower pivot) into pcl[j] and
+// that distance into pdist[j]; a pivot's wavefront also writes its row of
+// pivot-to-pivot distances into pp.
 __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
                               float *__restrict__ cent, float *__restrict__ lmax,
                               unsigned long long *__restrict__ counters, long long n_points,
@@ -41,38 +42,37 @@ __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
                               float *__restrict__ pp) {
     __shared__ double red[256];
     if ((int)blockIdx.x >= dp) {
-        const int j = ((int)blockIdx.x - dp) * (blockDim.x / 64) + (threadIdx.x >> 6);
-        const int lane = threadIdx.x & 63;
-        if (j >= g) return;
+        // pivot rows staged transposed (dimension-major: lanes read
+        // consecutive words), then ASSIGN_PER_BLOCK landmarks, one per
+        // wavefront at a time, lane = pivot
+        extern __shared__ float pvt[];  // d x 64
         const int P = order_pivots(g);
-        float dd = INFINITY;
-        if (lane < P) {
-            const int pv = (int)(((long long)lane * g) / P);
-            const float *Lj = L + (size_t)j * d, *Lp = L + (size_t)pv * d;
+        for (int e = threadIdx.x; e < d * 64; e += blockDim.x) {
+            const int q = e / 64, i = e % 64;
+            pvt[e] = i < P ? L[(size_t)(((long long)i * g) / P) * d + q] : 0.f;
+        }
+        __syncthreads();
+        const int lane = threadIdx.x & 63, wv = threadIdx.x >> 6;
+        const int j0 = ((int)blockIdx.x - dp) * ASSIGN_PER_BLOCK;
+        for (int j = j0 + wv; j < j0 + ASSIGN_PER_BLOCK && j < g; j += blockDim.x / 64) {
+            const float *Lj = L + (size_t)j * d;
             float s = 0.f;
             for (int q = 0; q < d; ++q) {
-                const float df = Lj[q] - Lp[q];
+                const float df = Lj[q] - pvt[q * 64 + lane];
                 s = fmaf(df, df, s);
             }
-            dd = s;
-        }
-        {
-            const int pi = (int)(((long long)j * P + g - 1) / g);  // the pivot j may be
-            if (pi < P && (int)(((long long)pi * g) / P) == j && lane < P) pp[pi * P + lane] = dd;
-        }
-        int bi = lane < P ? lane : 0x7fffffff;
-#pragma unroll
-        for (int o = 32; o > 0; o >>= 1) {
-            const float od = __shfl_xor(dd, o);
-            const int oi = __shfl_xor(bi, o);
-            if (od < dd || (od == dd && oi < bi)) {
-                dd = od;
-                bi = oi;
+            const float dd = lane < P ? s : INFINITY;
+            {
+                const int pi = (int)(((long long)j * P + g - 1) / g);  // the pivot j may be
+                if (pi < P && (int)(((long long)pi * g) / P) == j && lane < P) pp[pi * P + lane] = dd;
             }
-        }
-        if (lane == 0) {
-            pcl[j] = bi == 0x7fffffff ? 0 : bi;
-            pdist[j] = dd;
+            // nearest pivot: wave minimum of (distance bits, low 6 bits = pivot)
+            const unsigned kv = lane < P ? ((__float_as_uint(dd) & ~63u) | (unsigned)lane) : 0xffffffffu;
+            const int best = (int)(__ockl_wfred_min_u32(kv) & 63u);
+            if (lane == best) {
+                pcl[j] = best;
+                pdist[j] = dd;
+            }
         }
         return;
     }
@@ -148,11 +148,11 @@ __global__ void __launch_bounds__(1024) prep_order(int g, const int *__restrict_
 // One wavefront per (padded) landmark, lanes over dimensions: centred row,
 // squared norm (FP64 wave sum), MFMA operand entries, the zero-padded FP32
 // copy for exact rescoring, and the norm maximum.
-__global__ void prep_landmarks(const float *__restrict__ L, const int *__restrict__ perm, int g,
+__device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict__ L, const int *__restrict__ perm, int g,
                                int gpad, int d, int dp, int mode, const float *__restrict__ cent,
                                void *__restrict__ A, float *__restrict__ norms,
                                float *__restrict__ Lpad, float *__restrict__ lmax) {
-    const int j = blockIdx.x * (blockDim.x / 64) + (threadIdx.x >> 6);
+    const int j = blk * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (j >= gpad) return;
     const int t = j / TILE, m = j % TILE;
@@ -197,12 +197,12 @@ __global__ void prep_landmarks(const float *__restrict__ L, const int *__restric
 // written coalesced.
 constexpr int PAIR_TILE = 16;
 
-__global__ void __launch_bounds__(256) prep_pairs(const float *__restrict__ L,
-                                                  const int *__restrict__ perm, int g, int d,
-                                                  float *__restrict__ inv2) {
-    extern __shared__ float prs[];  // 2 x PAIR_TILE x (d + 1)
+__device__ __forceinline__ void prep_pairs(int blk, float *prs, const float *__restrict__ L,
+                                           const int *__restrict__ perm, int g, int d,
+                                           float *__restrict__ inv2) {
+    // prs: 2 x PAIR_TILE x (d + 1) floats of LDS
     const int ntu = (g + PAIR_TILE - 1) / PAIR_TILE;
-    const int u0 = (blockIdx.x / ntu) * PAIR_TILE, v0 = (blockIdx.x % ntu) * PAIR_TILE;
+    const int u0 = (blk / ntu) * PAIR_TILE, v0 = (blk % ntu) * PAIR_TILE;
     const int rs = d + 1;
     float *Lu = prs, *Lv = prs + PAIR_TILE * rs;
     for (int e = threadIdx.x; e < PAIR_TILE * d; e += blockDim.x) {
@@ -222,20 +222,35 @@ __global__ void __launch_bounds__(256) prep_pairs(const float *__restrict__ L,
     inv2[(size_t)u * g + v] = s > 0.0 ? (float)(0.5 / s) : -1.f;
 }
 
+// The landmark tables and the pair table in one launch: blocks 0 .. nlb-1
+// prepare 4 landmarks each, the others one 16 x 16 tile of pairs each.
+__global__ void __launch_bounds__(256) prep_tables(const float *__restrict__ L, const int *__restrict__ perm,
+                                                   int g, int gpad, int d, int dp, int mode, int nlb,
+                                                   const float *__restrict__ cent, void *__restrict__ A,
+                                                   float *__restrict__ norms, float *__restrict__ Lpad,
+                                                   float *__restrict__ lmax, float *__restrict__ inv2) {
+    extern __shared__ float prs[];
+    if ((int)blockIdx.x < nlb)
+        prep_landmarks((int)blockIdx.x, L, perm, g, gpad, d, dp, mode, cent, A, norms, Lpad, lmax);
+    else
+        prep_pairs((int)blockIdx.x - nlb, prs, L, perm, g, d, inv2);
+}
+
 hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long long *counters,
                        long long n_points, hipStream_t s) {
-    hipLaunchKernelGGL(prep_centroid, dim3(P.dp + (P.g + 3) / 4), dim3(256), 0, s, L, P.g, P.d, P.dp,
-                       P.cent, P.lmax, counters, n_points, P.pcl, P.pdist, P.ppiv);
+    hipLaunchKernelGGL(prep_centroid, dim3(P.dp + (P.g + ASSIGN_PER_BLOCK - 1) / ASSIGN_PER_BLOCK),
+                       dim3(256), sizeof(float) * P.d * 64, s, L, P.g, P.d, P.dp, P.cent, P.lmax, counters,
+                       n_points, P.pcl, P.pdist, P.ppiv);
     const size_t osm = sizeof(unsigned long long) * P.g + sizeof(float) * ORDER_MAX_P * ORDER_MAX_P +
                        sizeof(int) * ORDER_MAX_P;
     hipLaunchKernelGGL(prep_order, dim3(1), dim3(1024), osm, s, P.g, P.pcl, P.pdist, P.ppiv, P.perm,
                        P.ipos);
     const int gpad = P.ntiles * TILE;
-    hipLaunchKernelGGL(prep_landmarks, dim3((gpad + 3) / 4), dim3(256), 0, s, L, P.perm, P.g, gpad,
-                       P.d, P.dp, mode, P.cent, P.A, P.norms, P.Lpad, P.lmax);
+    const int nlb = (gpad + 3) / 4;
     const int ntu = (P.g + PAIR_TILE - 1) / PAIR_TILE;
-    hipLaunchKernelGGL(prep_pairs, dim3((unsigned)(ntu * ntu)), dim3(256),
-                       sizeof(float) * 2 * PAIR_TILE * (P.d + 1), s, L, P.perm, P.g, P.d, P.inv2);
+    hipLaunchKernelGGL(prep_tables, dim3((unsigned)(nlb + ntu * ntu)), dim3(256),
+                       sizeof(float) * 2 * PAIR_TILE * (P.d + 1), s, L, P.perm, P.g, gpad, P.d, P.dp, mode,
+                       nlb, P.cent, P.A, P.norms, P.Lpad, P.lmax, P.inv2);
     return hipGetLastError();
 }
 
@@ -269,7 +284,8 @@ __device__ __forceinline__ bool lex_less(double a, int ia, double b, int ib) {
 
 __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_points) {
     extern __shared__ __align__(16) unsigned char esm[];
-    double *dist = reinterpret_cast<double *>(esm);        // g
+    float *nrow = reinterpret_cast<float *>(esm);           // k x dp: the neighbours' rows
+    double *dist = reinterpret_cast<double *>(nrow + (size_t)a.k * a.dp);  // g
     double *xs = dist + a.g;                                // dp (zero beyond d)
     double *sel_d = xs + a.dp;                              // k
     double *sc = sel_d + ESOM_MAX_K;                        // k
@@ -415,7 +431,14 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
             }
         }
         __syncthreads();
-        // pairs spread over the threads
+        // the neighbours' rows into LDS (coalesced), then every pair's
+        // projection from them, spread over the threads
+        for (int e = tid; e < k * (a.dp / 4); e += EX_THREADS) {
+            const int q = e / (a.dp / 4), c = e % (a.dp / 4);
+            reinterpret_cast<float4 *>(nrow + (size_t)q * a.dp)[c] =
+                reinterpret_cast<const float4 *>(a.Lpad + (size_t)a.ipos[sel_j[q]] * a.dp)[c];
+        }
+        __syncthreads();
         double M00 = 0.0, M01 = 0.0, M11 = 0.0, r0 = 0.0, r1 = 0.0, ssum = 0.0;
         const int npair = k * (k - 1) / 2;
         for (int p = tid; p < npair && !degenerate; p += EX_THREADS) {
@@ -426,8 +449,8 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
             }
             const int qj = qi + 1 + rem;
             const int u = sel_j[qi], v = sel_j[qj];
-            const float *Lu = a.Lpad + (size_t)a.ipos[u] * a.dp;
-            const float *Lv = a.Lpad + (size_t)a.ipos[v] * a.dp;
+            const float *Lu = nrow + (size_t)qi * a.dp;
+            const float *Lv = nrow + (size_t)qj * a.dp;
             double HH = 0.0, xH = 0.0;
             for (int q = 0; q < a.d; ++q) {
                 const double H = (double)Lv[q] - (double)Lu[q];
@@ -507,7 +530,7 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
 
 static size_t exact_smem(const EmbedArgs &a) {
     return sizeof(double) * ((size_t)a.g + a.dp + 2 * ESOM_MAX_K + 6 * (EX_THREADS / 64)) +
-           sizeof(int) * (ESOM_MAX_K + 2 * EX_SEL_CAP + 2);
+           sizeof(int) * (ESOM_MAX_K + 2 * EX_SEL_CAP + 4) + sizeof(float) * (size_t)a.k * a.dp;
 }
 
 hipError_t launch_fallback(const EmbedArgs &a, int num_cus, hipStream_t s) {

@@ -43,7 +43,6 @@ typedef __bf16 bf16x8 __attribute__((ext_vector_type(8)));
 typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 
 constexpr float U32 = 5.9604645e-08f;     // 2^-24, FP32 unit roundoff
-constexpr float UBF16 = 0.00390625f;      // 2^-8, BF16 unit roundoff
 constexpr float ILL_PAIR = 64.0f;         // max(delta^2)/(2|L_u-L_v|^2) beyond this: exact path
 constexpr double ILL_COND = 64.0;         // (tr/2)^2/det beyond this: exact path
 
@@ -82,26 +81,97 @@ __device__ __forceinline__ float kth_bound(float d2k, int dp) {
     return t < FLT_MAX ? t : INFINITY;
 }
 
-// Ascending bitonic sort of N non-negative floats given as their bit
-// patterns (for those, integer order is float order; +inf sorts last).
+// Batcher's odd-even merge sort network on N = 2^m inputs (63 comparators for
+// 16, 191 for 32), built at compile time.
 template <int N>
-__device__ __forceinline__ void sort_regs(int (&v)[N]) {
-#pragma unroll
-    for (int k = 2; k <= N; k <<= 1) {
-#pragma unroll
-        for (int j = k >> 1; j > 0; j >>= 1) {
-#pragma unroll
-            for (int i = 0; i < N; ++i) {
-                const int l = i ^ j;
-                if (l > i) {
-                    const int a = v[i], b = v[l];
-                    const bool up = (i & k) == 0;
-                    v[i] = up ? min(a, b) : max(a, b);
-                    v[l] = up ? max(a, b) : min(a, b);
-                }
+struct OemNet {
+    int a[N * N] = {}, b[N * N] = {};
+    int n = 0;
+    constexpr OemNet() { sort(0, N - 1); }
+    constexpr void merge(int lo, int hi, int r) {
+        const int step = 2 * r;
+        if (step < hi - lo) {
+            merge(lo, hi, step);
+            merge(lo + r, hi, step);
+            for (int i = lo + r; i < hi - r; i += step) {
+                a[n] = i;
+                b[n] = i + r;
+                ++n;
             }
+        } else {
+            a[n] = lo;
+            b[n] = lo + r;
+            ++n;
         }
     }
+    constexpr void sort(int lo, int hi) {
+        if (hi - lo >= 1) {
+            const int mid = lo + (hi - lo) / 2;
+            sort(lo, mid);
+            sort(mid + 1, hi);
+            merge(lo, hi, 1);
+        }
+    }
+};
+
+// Ascending sort of N registers.  The screen sorts bit patterns of
+// non-negative floats: for those, integer order is float order and +inf sorts
+// last.
+template <int N>
+__device__ __forceinline__ void sort_regs(int (&v)[N]) {
+    constexpr OemNet<N> net{};
+#pragma unroll
+    for (int c = 0; c < net.n; ++c) {
+        const int x = v[net.a[c]], y = v[net.b[c]];
+        v[net.a[c]] = min(x, y);
+        v[net.b[c]] = max(x, y);
+    }
+}
+
+// The j-th smallest (1 <= j <= 32) of the 32 values lo[0..15], hi[0..15].
+// For j <= 16: with both halves sorted, min(lo[i], hi[15 - i]) holds the 16
+// smallest of the union as a bitonic sequence; its maximum is the 16th
+// smallest, and a bitonic merge orders it for smaller j.  j is uniform.
+__device__ __forceinline__ int select_jth(int (&lo)[16], int (&hi)[16], int j) {
+    if (j <= 16) {
+        sort_regs<16>(lo);
+        sort_regs<16>(hi);
+        int m[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) m[i] = min(lo[i], hi[15 - i]);
+        if (j == 16) {
+            int t = m[0];
+#pragma unroll
+            for (int i = 1; i < 16; ++i) t = max(t, m[i]);
+            return t;
+        }
+#pragma unroll
+        for (int st = 8; st > 0; st >>= 1)
+#pragma unroll
+            for (int i = 0; i < 16; ++i)
+                if ((i & st) == 0) {
+                    const int x = m[i], y = m[i + st];
+                    m[i] = min(x, y);
+                    m[i + st] = max(x, y);
+                }
+        int t = m[0];
+#pragma unroll
+        for (int i = 1; i < 16; ++i)
+            if (i == j - 1) t = m[i];
+        return t;
+    }
+    int v[32];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        v[i] = lo[i];
+        v[16 + i] = hi[i];
+    }
+    sort_regs<32>(v);
+    int t = v[31];
+#pragma unroll
+    for (int i = 16; i < 32; ++i)
+        if (i == j - 1) t = v[i];
+    return t;
 }
 
 // FP64 minimum / maximum as single instructions.  fmin/fmax would add a
@@ -309,50 +379,72 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
     }
     if (!(ssum > 0.f)) reason |= R_DEGEN;
 
-    // pairs (i < j among the neighbours with non-zero score); d2i <= d2j
-    bool ill = false;
+    // pairs (i < j among the neighbours with non-zero score); d2i <= d2j.  The
+    // pair (i, j) adds q/|h|^2 h h^T to M and q/|h|^2 h t to r, with h = l_j - l_i,
+    // t = D |h|^2 + h.l_i and D its segment coordinate.  Split as q D h plus
+    // (q/|h|^2 h h^T) l_i, the second part sums over j into M_i l_i, so a pair
+    // costs no dot product; s_i multiplies the sums of base i once.  The pair
+    // table supplies 1/(2|L_u - L_v|^2) and 1/|h|^2, both 0 for a skipped pair,
+    // so a skipped pair adds exactly 0.
+    float pmax = 0.f;  // largest delta_j^2 / (2 |L_i - L_j|^2) over the pairs
     const bool unit_adjust = a.adjust == 1.0f;
-    // unit: adjust == 1 (weight 1 / |h|^2), as a compile-time tag so that the
-    // two variants of the pair loop are separate code
-    auto pair_term = [&](auto unit, float d2i, float si, float lxi, float lyi, float d2j, float sj,
-                         float lxj, float lyj, float inv) {
+    auto pair_term = [&](auto unit, float d2i, float lxi, float lyi, float d2j, float sj, float lxj,
+                         float lyj, float2 pv, float (&Mi)[3], float (&ri)[2]) {
+        const float inv = pv.x, ihh = pv.y;
         const float hx = lxj - lxi, hy = lyj - lyi;
-        const float hh = fmaf(hx, hx, hy * hy);
-        const bool skip = inv < 0.f || hh == 0.f;
-        const float hs = skip ? 1.f : hh;
-        ill |= !skip && d2j * inv > ILL_PAIR;
         const float D = fmaf(d2i - d2j, inv, 0.5f);
-        const float ihh = __builtin_amdgcn_rcpf(hs);
-        float w;
+        pmax = fmaxf(pmax, d2j * inv);
+        float q;
+        // unit: adjust == 1 (weight 1 / |h|^2), as a compile-time tag so that
+        // the two variants of the pair loop are separate code
         if constexpr (decltype(unit)::value)
-            w = ihh;
+            q = sj * ihh;
         else
-            w = exp2f(-a.adjust * __log2f(hs));
-        const float q = skip ? 0.f : si * sj * w;
-        const float qh = q * ihh;
-        const float t = fmaf(D, hs, fmaf(hx, lxi, hy * lyi));
+            q = ihh > 0.f ? sj * exp2f(a.adjust * __log2f(ihh)) : 0.f;
+        const float qh = q * ihh, qD = q * D;
         const float qhx = qh * hx, qhy = qh * hy;
-        M00 = fmaf(qhx, hx, M00);
-        M01 = fmaf(qhx, hy, M01);
-        M11 = fmaf(qhy, hy, M11);
-        r0 = fmaf(qhx, t, r0);
-        r1 = fmaf(qhy, t, r1);
+        Mi[0] = fmaf(qhx, hx, Mi[0]);
+        Mi[1] = fmaf(qhx, hy, Mi[1]);
+        Mi[2] = fmaf(qhy, hy, Mi[2]);
+        ri[0] = fmaf(qD, hx, ri[0]);
+        ri[1] = fmaf(qD, hy, ri[1]);
+    };
+    // closes base i: r += s_i (r_i + M_i l_i), M += s_i M_i
+    auto close_base = [&](bool origin, float si, float lxi, float lyi, const float (&Mi)[3],
+                          float (&ri)[2]) {
+        if (!origin) {
+            ri[0] = fmaf(Mi[0], lxi, fmaf(Mi[1], lyi, ri[0]));
+            ri[1] = fmaf(Mi[1], lxi, fmaf(Mi[2], lyi, ri[1]));
+        }
+        M00 = fmaf(si, Mi[0], M00);
+        M01 = fmaf(si, Mi[1], M01);
+        M11 = fmaf(si, Mi[2], M11);
+        r0 = fmaf(si, ri[0], r0);
+        r1 = fmaf(si, ri[1], r1);
     };
     auto run_pairs = [&](auto unit) {
     if constexpr (KP <= 16) {
-        // neighbour data in registers; each row of pair-table loads is issued together
+        // neighbour data in registers; each row of pair-table loads is issued
+        // together, unconditionally (slots past k hold landmark 0, a valid
+        // entry, and are never used), addressed by 32-bit byte offsets from
+        // the table base (g <= 4096: under 2^31 bytes)
+        const char *ptab = reinterpret_cast<const char *>(a.pairs);
 #pragma unroll
         for (int qi = 0; qi < KP - 1; ++qi) {
             if (qi < a.kact - 1) {
-                const float *invrow = a.inv2 + (size_t)iposL[jq[qi]] * a.g;
-                float inv[KP];
+                const unsigned rowoff = (unsigned)iposL[jq[qi]] * (unsigned)a.g;
+                float2 pv[KP];
 #pragma unroll
-                for (int qj = qi + 1; qj < KP; ++qj) inv[qj] = (qj < a.kact) ? invrow[iposL[jq[qj]]] : -1.f;
+                for (int qj = qi + 1; qj < KP; ++qj)
+                    pv[qj] = *reinterpret_cast<const float2 *>(ptab + (size_t)((rowoff + iposL[jq[qj]]) * 8u));
+                float Mi[3] = {0.f, 0.f, 0.f}, ri[2] = {0.f, 0.f};
 #pragma unroll
                 for (int qj = qi + 1; qj < KP; ++qj)
                     if (qj < a.kact)
-                        pair_term(unit, d2q[qi], sq[qi], lxq[qi], lyq[qi], d2q[qj], sq[qj], lxq[qj],
-                                  lyq[qj], inv[qj]);
+                        pair_term(unit, d2q[qi], lxq[qi], lyq[qi], d2q[qj], sq[qj], lxq[qj], lyq[qj],
+                                  pv[qj], Mi, ri);
+                // neighbour 0 is the origin of the 2-D frame
+                close_base(qi == 0, sq[qi], lxq[qi], lyq[qi], Mi, ri);
             }
         }
     } else {
@@ -371,15 +463,17 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
             const int ui = nbI[qi * 64 + lane];
             const float2 li = reinterpret_cast<const float2 *>(a.l2d)[ui];
             const float lxi = li.x - ox, lyi = li.y - oy;
-            const float *invrow = a.inv2 + (size_t)iposL[ui] * a.g;
+            const float2 *prow = a.pairs + (size_t)iposL[ui] * a.g;
+            float Mi[3] = {0.f, 0.f, 0.f}, ri[2] = {0.f, 0.f};
             for (int qb = qi + 1; qb < a.kact; qb += 4) {
-                float inv[4], d2j[4], sj[4], lxj[4], lyj[4];
+                float2 pv[4];
+                float d2j[4], sj[4], lxj[4], lyj[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
                     const int qj = qb + u;
                     const bool ok = qj < a.kact;
                     const int vj = ok ? nbI[qj * 64 + lane] : 0;
-                    inv[u] = ok ? invrow[iposL[vj]] : -1.f;
+                    pv[u] = ok ? prow[iposL[vj]] : make_float2(0.f, 0.f);
                     d2j[u] = ok ? nbD2[qj * 64 + lane] : 0.f;
                     sj[u] = ok ? nbS[qj * 64 + lane] : 0.f;
                     const float2 lv = reinterpret_cast<const float2 *>(a.l2d)[vj];
@@ -388,8 +482,9 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
                 }
 #pragma unroll
                 for (int u = 0; u < 4; ++u)
-                    pair_term(unit, d2i, si, lxi, lyi, d2j[u], sj[u], lxj[u], lyj[u], inv[u]);
+                    pair_term(unit, d2i, lxi, lyi, d2j[u], sj[u], lxj[u], lyj[u], pv[u], Mi, ri);
             }
+            close_base(false, si, lxi, lyi, Mi, ri);
         }
         __builtin_amdgcn_wave_barrier();
     }
@@ -398,6 +493,7 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
         run_pairs(BoolTag<true>{});
     else
         run_pairs(BoolTag<false>{});
+    const bool ill = pmax > ILL_PAIR;
     // 2x2 solve in FP64 (Cramer's rule)
     const double m00 = M00, m01 = M01, m11 = M11, rr0 = r0, rr1 = r1;
     const double det = m00 * m11 - m01 * m01;
@@ -494,12 +590,11 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
     unsigned short *nbI = reinterpret_cast<unsigned short *>(nbS + KP * 64);
     const int nbr_bytes = KP > 16 ? KP * 64 * 10 : 0;
     const int tail = (2 * W * 64 * 4 > nbr_bytes) ? 2 * W * 64 * 4 : nbr_bytes;
-    float *tauL = reinterpret_cast<float *>(wsm + tail);
-    float *xnL = tauL + 64;
-    unsigned long long *maskL = reinterpret_cast<unsigned long long *>(xnL + 64);
+    float *certL = reinterpret_cast<float *>(wsm + tail);  // 64 certificate bounds (512 B reserved)
+    unsigned long long *maskL = reinterpret_cast<unsigned long long *>(certL + 128);
 
-    const float lmax = *a.lmax;
-    const float us = (MODE == 1) ? UBF16 : U32;
+    const float lmax = a.lmax[0];
+    const float qa = a.lmax[1];  // max_j |bf16(-2 (L_j - c)) + 2 (L_j - c)|
 
     unsigned long long st_cand = 0;
     const int64_t nwt = (a.n + 63) / 64;
@@ -508,13 +603,13 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
 
         // ---------------- point operands (centred), and |x - c|^2
         PointOperand<MODE, DC> P;
-        float xnp[2];
+        float xnp[2], dxp[2];  // |x - c|^2 and, in BF16 mode, |bf16(x - c) - (x - c)|^2
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             const int64_t pi = pbase + 32 * p + i32;
             const bool valid = pi < a.n;
             const float *xr = a.X + (valid ? pi : 0) * a.ldx;
-            float part = 0.f;
+            float part = 0.f, dpart = 0.f;
             if constexpr (MODE == 1) {
 #pragma unroll
                 for (int c = 0; c < DC; ++c) {
@@ -540,7 +635,12 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                         }
                         part = fmaf(v0, v0, part);
                         part = fmaf(v1, v1, part);
-                        w[e >> 1] = bf16_bits_rne(v0) | (bf16_bits_rne(v1) << 16);
+                        const unsigned b0 = bf16_bits_rne(v0), b1 = bf16_bits_rne(v1);
+                        // quantisation errors (exact in FP32)
+                        const float q0 = __uint_as_float(b0 << 16) - v0, q1 = __uint_as_float(b1 << 16) - v1;
+                        dpart = fmaf(q0, q0, dpart);
+                        dpart = fmaf(q1, q1, dpart);
+                        w[e >> 1] = b0 | (b1 << 16);
                     }
                     u32x4 wv = {w[0], w[1], w[2], w[3]};
                     P.b[p][c] = __builtin_bit_cast(bf16x8, wv);
@@ -555,6 +655,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 }
             }
             xnp[p] = part + __shfl_xor(part, 32);
+            dxp[p] = (MODE == 1) ? dpart + __shfl_xor(dpart, 32) : 0.f;
         }
 
         // ---------------- pass 1: group minima of the approximate squared distances
@@ -593,16 +694,13 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         float tau[2], taucert[2];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            int v[32];
+            int v0[16], v1[16];
 #pragma unroll
-            for (int q = 0; q < 2; ++q)
-#pragma unroll
-                for (int r = 0; r < 16; ++r) v[16 * q + r] = max(gmin[p][q][r], 0);
-            sort_regs<32>(v);
-            int tl = v[31];
-#pragma unroll
-            for (int q = 0; q < 32; ++q)
-                if (q == a.jsel - 1) tl = v[q];
+            for (int r = 0; r < 16; ++r) {
+                v0[r] = max(gmin[p][0][r], 0);
+                v1[r] = max(gmin[p][1][r], 0);
+            }
+            int tl = select_jth(v0, v1, a.jsel);
             tl = min(tl, 0x7F7FFFFF);  // +inf (too few landmarks) -> FLT_MAX
             const float own = __int_as_float(tl), oth = __int_as_float(__shfl_xor(tl, 32));
             const float tb = MODE == 1 ? own : fmaxf(own, oth);
@@ -644,11 +742,32 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 pass2_store(tp);
             }
         }
+        // Certificate bound per point: a non-candidate's exact distance^2 exceeds
+        // tau + |x - c|^2 - E, E a rigorous bound of the screen's error.  With
+        // a = -2(L - c) and its BF16 image a + da, x' = x - c and its BF16 image
+        // x' + dx: |x'.da + dx.a + dx.da| <= |x'| max|da| + |dx| (max|a| + max|da|)
+        // (|dx| exact per point, max|da| from the preparation); plus FP32
+        // accumulation and centring, (2 d_pad + 16) u (|x'| + max|L - c|)^2.  In
+        // FP32 mode the operands are exact and 2 (2u + u^2) |x'| max|L - c| bounds
+        // the products.  The FP32 evaluation of the bound is covered by 1.01 and
+        // by 4u of the terms.
         if (h == 0) {
-            tauL[i32] = taucert[0];
-            tauL[32 + i32] = taucert[1];
-            xnL[i32] = xnp[0];
-            xnL[32 + i32] = xnp[1];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const float sx = sqrtf(xnp[p]);
+                const float facc = (2.f * DP + 16.f) * U32 * (sx + lmax) * (sx + lmax);
+                float E;
+                if constexpr (MODE == 1) {
+                    const float dx = sqrtf(dxp[p]);
+                    E = 1.01f * (sx * qa + dx * (2.f * lmax + qa) + facc);
+                } else {
+                    E = 1.01f * (2.f * (2.f * U32 + U32 * U32) * sx * lmax + facc);
+                }
+                const float tc = taucert[p];
+                float rhs = tc + xnp[p] - E;
+                rhs -= 4.f * U32 * (fabsf(tc) + xnp[p] + E);
+                certL[32 * p + i32] = (tc >= FLT_MAX) ? INFINITY : rhs;
+            }
         }
         // masks of lane (screen half h, point i32) for point groups p = 0, 1
         maskL[(0 * 2 + h) * 32 + i32] = nonempty[0];
@@ -660,8 +779,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         // ---------------- phase B: one lane per point (lane l <-> point pbase + l)
         const int64_t pi = pbase + lane;
         const bool valid = pi < a.n;
-        const float tau_p = tauL[lane];
-        const float xn = xnL[lane];
+        const float cert_rhs = certL[lane];
         float x[DP];
         {
             const float *xr = a.X + (valid ? pi : 0) * a.ldx;
@@ -710,9 +828,8 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 if (__ballot(act) == 0ull) break;
                 const int pos = __clz((int)b);
                 b &= ~(0x80000000u >> pos);
-                const int t = 2 * ctp + (pos >> 4);
-                const int r = pos & 15;
-                const int j = act ? 32 * t + 8 * (r >> 2) + 4 * chh + (r & 3) : 0;
+                // bit pos of a word of tile pair ctp, screen half chh
+                const int j = act ? 64 * ctp + 2 * pos + chh : 0;
                 float acc = 0.f;
                 if (a.lds_rows) {
                     const float4 *Lr = reinterpret_cast<const float4 *>(rowsL + (size_t)j * RS);
@@ -758,12 +875,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
 
         unsigned reason = 0;
         {
-            const float sx = sqrtf(xn);
-            const float E = 1.01f * (2.f * (2.f * us + us * us) * sx * lmax +
-                                     (2.f * DP + 16.f) * U32 * (sx + lmax) * (sx + lmax));
-            float rhs = tau_p + xn - E;
-            rhs -= 4.f * U32 * (fabsf(tau_p) + xn + E);
-            const bool cert = (tau_p >= FLT_MAX) || (d2k * (1.f + (DP + 3) * U32) < rhs);
+            const bool cert = d2k * (1.f + (DP + 3) * U32) < cert_rhs;
             if (!cert || m < a.k) reason |= R_UNCERT;
             // two rescored values are ordered correctly when their gap exceeds the sum
             // of their rounding bounds, (d_pad + 3) u each

@@ -92,8 +92,8 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp) {
     sc.prep.A = take(sizeof(float) * (size_t)ntiles * TILE * dp);
     sc.prep.norms = static_cast<float *>(take(sizeof(float) * (size_t)ntiles * TILE));
     sc.prep.Lpad = static_cast<float *>(take(sizeof(float) * (size_t)g * dp));
-    sc.prep.inv2 = static_cast<float *>(take(sizeof(float) * (size_t)g * g));
-    sc.prep.lmax = static_cast<float *>(take(sizeof(float)));
+    sc.prep.pairs = static_cast<float2 *>(take(sizeof(float2) * (size_t)g * g));
+    sc.prep.lmax = static_cast<float *>(take(2 * sizeof(float)));
     sc.prep.perm = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
     sc.prep.ipos = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
     sc.prep.pcl = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
@@ -200,7 +200,7 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
         }
         (void)hipEventRecord(ev[0], s);
     }
-    hipError_t e = launch_prep(pr, L, P.mode, c->counters, knn_only ? 0 : (long long)n, s);
+    hipError_t e = launch_prep(pr, L, knn_only ? nullptr : l2d, P.mode, c->counters, knn_only ? 0 : (long long)n, s);
     if (e != hipSuccess) return hip_fail(e, "landmark preparation launch");
     if (timed) (void)hipEventRecord(ev[1], s);
 
@@ -219,7 +219,7 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
     a.cent = pr.cent;
     a.Lpad = pr.Lpad;
     a.l2d = l2d;
-    a.inv2 = pr.inv2;
+    a.pairs = pr.pairs;
     a.lmax = pr.lmax;
     a.perm = pr.perm;
     a.ipos = pr.ipos;
@@ -247,17 +247,17 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
         e = launch_project(a, pl.kp, c->num_cus, s);
         if (e != hipSuccess) return hip_fail(e, "projection kernel launch");
         if (timed) (void)hipEventRecord(ev[2], s);
-        e = launch_fallback(a, c->num_cus, s);
+        e = launch_fallback(a, c->num_cus, c->lds_per_block, s);
         if (e != hipSuccess) return hip_fail(e, "exact-path launch");
     } else if (pl.fast) {
         e = launch_embed(a, P.mode, pl.kp, c->num_cus, c->lds_per_block, s);
         if (e != hipSuccess) return hip_fail(e, "embed kernel launch");
         if (timed) (void)hipEventRecord(ev[2], s);
-        e = launch_fallback(a, c->num_cus, s);
+        e = launch_fallback(a, c->num_cus, c->lds_per_block, s);
         if (e != hipSuccess) return hip_fail(e, "exact-path launch");
     } else {
         if (timed) (void)hipEventRecord(ev[2], s);
-        e = launch_all_to_fallback(a, c->num_cus, s);
+        e = launch_all_to_fallback(a, c->num_cus, c->lds_per_block, s);
         if (e != hipSuccess) return hip_fail(e, "exact-path launch");
     }
     if (timed) {

@@ -30,7 +30,8 @@ __host__ __device__ inline int order_pivots(int g) { return g < ORDER_MAX_P ? g 
 
 // Centroid of the landmarks (FP64 sum, rounded to FP32), zero-padded to dp:
 // blocks 0 .. dp-1, one per dimension.  Block 0 also resets the per-call
-// fallback list and the landmark norm maximum, and counts the points of this
+// fallback list and the landmark maxima (norm, BF16 quantisation error of the
+// MFMA operand), and counts the points of this
 // call.  Blocks dp .. : the landmarks' nearest pivots (squared FP32
 // distance; equal leading bits break to the lower pivot) into pcl[j] and
 // that distance into pdist[j]; a pivot's wavefront also writes its row of
@@ -88,7 +89,8 @@ __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
     }
     if (threadIdx.x == 0) cent[t] = t < d ? (float)(red[0] / (double)g) : 0.f;
     if (t == 0 && threadIdx.x == 0) {
-        *lmax = 0.f;
+        lmax[0] = 0.f;
+        lmax[1] = 0.f;
         counters[C_FB_LEN] = 0ull;
         counters[C_POINTS] += (unsigned long long)n_points;
     }
@@ -155,11 +157,18 @@ __device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict_
     const int j = blk * (blockDim.x / 64) + (threadIdx.x >> 6);
     const int lane = threadIdx.x & 63;
     if (j >= gpad) return;
-    const int t = j / TILE, m = j % TILE;
+    // Position j sits in tile pair j / 64, screen half j % 2, tile parity
+    // (j / 32) % 2 and accumulator register (j / 2) % 16, so that bit b of a
+    // candidate-bitmap word (16 parity + register) is position
+    // 64 tile_pair + 2 b + half: the two halves of a point's screen
+    // interleave, and each sees every other landmark of the order.  MFMA 32x32
+    // output row m sits in lane half (m / 4) % 2, register 4 (m / 8) + m % 4.
+    const int rr = (j / 2) % 16, hj = j % 2;
+    const int t = 2 * (j / 64) + (j / 32) % 2, m = 8 * (rr >> 2) + 4 * hj + (rr & 3);
     const int dc = dp / 16;
     const bool real = j < g;
     const size_t src = real ? (size_t)perm[j] * d : 0;
-    double nrm = 0.0;
+    double nrm = 0.0, qe = 0.0;  // |L_j - c|^2, |BF16 quantisation error of -2 (L_j - c)|^2
     for (int q = lane; q < dp; q += 64) {
         const float lv = (real && q < d) ? L[src + q] : 0.f;
         const float c = (real && q < d) ? lv - cent[q] : 0.f;
@@ -171,6 +180,8 @@ __device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict_
             const int cc = q / 16, hh = (q % 16) / 8, e = q % 8;
             unsigned u = __float_as_uint(a2);
             u += 0x7FFFu + ((u >> 16) & 1u);
+            const double qd = (double)__uint_as_float(u & 0xFFFF0000u) - (double)a2;
+            qe += qd * qd;
             reinterpret_cast<unsigned short *>(A)[(((size_t)t * dc + cc) * 64 + 32 * hh + m) * 8 + e] =
                 (unsigned short)(u >> 16);
         } else {
@@ -180,35 +191,48 @@ __device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict_
         }
     }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) nrm += __shfl_xor(nrm, o);
+    for (int o = 32; o > 0; o >>= 1) {
+        nrm += __shfl_xor(nrm, o);
+        qe += __shfl_xor(qe, o);
+    }
     if (lane == 0) {
-        // MFMA 32x32 output row m sits in lane half h = (m / 4) % 2, register r = 4 (m / 8) + m % 4
-        const int hh = (m / 4) % 2, r = 4 * (m / 8) + m % 4;
-        norms[((size_t)t * 2 + hh) * 16 + r] = real ? (float)nrm : INFINITY;
-        if (real)
+        norms[((size_t)t * 2 + hj) * 16 + rr] = real ? (float)nrm : INFINITY;
+        if (real) {
             atomicMax(reinterpret_cast<unsigned *>(lmax), __float_as_uint((float)sqrt(nrm) * 1.0000002f));
+            atomicMax(reinterpret_cast<unsigned *>(lmax) + 1, __float_as_uint((float)sqrt(qe) * 1.0000002f));
+        }
     }
 }
 
-// Pair table inv2[u][v] = 1 / (2 |L_u - L_v|^2) (FP64 differences), -1 when
-// zero, indexed by landmark positions.  A 256-thread block computes a 16 x 16 tile of pairs from the two
+// Pair table pairs[u][v] = (1 / (2 |L_u - L_v|^2), 1 / |l_v - l_u|^2): the
+// high-dimensional factor of the segment coordinate (Section 3, the
+// projection of a point onto the segment between two landmarks) and the
+// inverse squared 2-D segment length, both from FP64 differences and both 0
+// for a skipped pair; indexed by landmark positions.  Each entry depends only
+// on the two landmarks, so the per-point pair loop needs no division.  A
+// 256-thread block computes a 16 x 16 tile of pairs from the two
 // 16-row slices of L staged in LDS (row stride d + 1 floats: no bank
 // conflicts between the 16 rows a wave reads); rows are read and the table
 // written coalesced.
 constexpr int PAIR_TILE = 16;
 
 __device__ __forceinline__ void prep_pairs(int blk, float *prs, const float *__restrict__ L,
-                                           const int *__restrict__ perm, int g, int d,
-                                           float *__restrict__ inv2) {
-    // prs: 2 x PAIR_TILE x (d + 1) floats of LDS
+                                           const float *__restrict__ l2d, const int *__restrict__ perm,
+                                           int g, int d, float2 *__restrict__ pairs) {
+    // prs: 2 x PAIR_TILE x (d + 1) floats of LDS, then 2 x PAIR_TILE 2-D positions
     const int ntu = (g + PAIR_TILE - 1) / PAIR_TILE;
     const int u0 = (blk / ntu) * PAIR_TILE, v0 = (blk % ntu) * PAIR_TILE;
     const int rs = d + 1;
     float *Lu = prs, *Lv = prs + PAIR_TILE * rs;
+    float2 *lu2 = reinterpret_cast<float2 *>(prs + 2 * PAIR_TILE * rs);  // 2 PAIR_TILE rs is even
     for (int e = threadIdx.x; e < PAIR_TILE * d; e += blockDim.x) {
         const int r = e / d, q = e % d;
         Lu[r * rs + q] = u0 + r < g ? L[(size_t)perm[u0 + r] * d + q] : 0.f;
         Lv[r * rs + q] = v0 + r < g ? L[(size_t)perm[v0 + r] * d + q] : 0.f;
+    }
+    if (l2d && threadIdx.x < 2 * PAIR_TILE) {
+        const int r = threadIdx.x % PAIR_TILE, w = (threadIdx.x < PAIR_TILE ? u0 : v0) + r;
+        lu2[threadIdx.x] = w < g ? reinterpret_cast<const float2 *>(l2d)[perm[w]] : make_float2(0.f, 0.f);
     }
     __syncthreads();
     const int ty = threadIdx.x / PAIR_TILE, tx = threadIdx.x % PAIR_TILE;
@@ -219,7 +243,19 @@ __device__ __forceinline__ void prep_pairs(int blk, float *prs, const float *__r
         const double df = (double)Lv[tx * rs + q] - (double)Lu[ty * rs + q];
         s = fma(df, df, s);
     }
-    inv2[(size_t)u * g + v] = s > 0.0 ? (float)(0.5 / s) : -1.f;
+    // a pair is skipped (both entries 0) when its high-dimensional or its 2-D
+    // landmarks coincide; the 2-D part is absent for k-NN-only calls
+    float iv = 0.f, w = 0.f;
+    if (s > 0.0 && l2d) {
+        const float2 lu = lu2[ty], lv = lu2[PAIR_TILE + tx];
+        const double hx = (double)lv.x - (double)lu.x, hy = (double)lv.y - (double)lu.y;
+        const double hh = fma(hx, hx, hy * hy);
+        if (hh > 0.0) {
+            iv = (float)(0.5 / s);
+            w = (float)(1.0 / hh);
+        }
+    }
+    pairs[(size_t)u * g + v] = make_float2(iv, w);
 }
 
 // The landmark tables and the pair table in one launch: blocks 0 .. nlb-1
@@ -228,16 +264,17 @@ __global__ void __launch_bounds__(256) prep_tables(const float *__restrict__ L, 
                                                    int g, int gpad, int d, int dp, int mode, int nlb,
                                                    const float *__restrict__ cent, void *__restrict__ A,
                                                    float *__restrict__ norms, float *__restrict__ Lpad,
-                                                   float *__restrict__ lmax, float *__restrict__ inv2) {
-    extern __shared__ float prs[];
+                                                   float *__restrict__ lmax, const float *__restrict__ l2d,
+                                                   float2 *__restrict__ pairs) {
+    extern __shared__ __align__(16) float prs[];
     if ((int)blockIdx.x < nlb)
         prep_landmarks((int)blockIdx.x, L, perm, g, gpad, d, dp, mode, cent, A, norms, Lpad, lmax);
     else
-        prep_pairs((int)blockIdx.x - nlb, prs, L, perm, g, d, inv2);
+        prep_pairs((int)blockIdx.x - nlb, prs, L, l2d, perm, g, d, pairs);
 }
 
-hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long long *counters,
-                       long long n_points, hipStream_t s) {
+hipError_t launch_prep(const Prep &P, const float *L, const float *l2d, int mode,
+                       unsigned long long *counters, long long n_points, hipStream_t s) {
     hipLaunchKernelGGL(prep_centroid, dim3(P.dp + (P.g + ASSIGN_PER_BLOCK - 1) / ASSIGN_PER_BLOCK),
                        dim3(256), sizeof(float) * P.d * 64, s, L, P.g, P.d, P.dp, P.cent, P.lmax, counters,
                        n_points, P.pcl, P.pdist, P.ppiv);
@@ -249,8 +286,8 @@ hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long lo
     const int nlb = (gpad + 3) / 4;
     const int ntu = (P.g + PAIR_TILE - 1) / PAIR_TILE;
     hipLaunchKernelGGL(prep_tables, dim3((unsigned)(nlb + ntu * ntu)), dim3(256),
-                       sizeof(float) * 2 * PAIR_TILE * (P.d + 1), s, L, P.perm, P.g, gpad, P.d, P.dp, mode,
-                       nlb, P.cent, P.A, P.norms, P.Lpad, P.lmax, P.inv2);
+                       sizeof(float) * 2 * PAIR_TILE * (P.d + 1) + sizeof(float2) * 2 * PAIR_TILE, s, L, P.perm, P.g, gpad, P.d, P.dp, mode,
+                       nlb, P.cent, P.A, P.norms, P.Lpad, P.lmax, l2d, P.pairs);
     return hipGetLastError();
 }
 
@@ -262,47 +299,125 @@ __device__ __forceinline__ double wave_sum(double v) {
     return v;
 }
 
-// Recomputes points exactly in FP64, one block of EX_THREADS per point:
+// Recomputes points exactly in FP64, one block of EX_THREADS per point (a
+// point's latency sets the duration of the short lists the fast kernel
+// leaves, so its work is spread over a block):
 //  1. all g distances from FP64 differences into LDS; the landmarks within
 //     the point's k-th distance bound (fb_thresh) are collected;
-//  2. the k nearest by (distance, index): each collected landmark's rank is
-//     counted against the others (few of them); with no usable bound (or too
-//     many within it) one wavefront takes k repeated (distance, index) minima
-//     over all g instead;
-//  3. the scores; every pair's segment projection from the coordinates,
-//     spread over the threads; block sums;
-//  4. Cramer's rule, or the centroid of the neighbours' 2-D positions for a
+//  2. without a usable bound (none given, or too few or too many within it),
+//     the k-th smallest of the threads' own minima bounds the k-th distance
+//     (those minima belong to distinct landmarks), and the landmarks within
+//     that bound are collected instead;
+//  3. the k nearest by (distance, index): each collected landmark's rank is
+//     counted against the others; only when too many remain collected does
+//     one wavefront take k repeated (distance, index) minima over all g;
+//  4. the scores (one neighbour per lane of wavefront 0); the neighbours'
+//     rows and 2-D positions into LDS; every pair's segment projection from
+//     the coordinates, spread over the threads; block sums;
+//  5. Cramer's rule, or the centroid of the neighbours' 2-D positions for a
 //     degenerate neighbourhood.
 // all_points = 1 processes every point (shapes outside the fast kernels),
 // otherwise the fast kernel's list.
 constexpr int EX_THREADS = 256;
 constexpr int EX_SEL_CAP = 256;  // collected landmarks ranked by counting
 
+// LDS layout (byte offsets).
+struct ExLayout {
+    size_t nrow, dist, xs, cdist, seld, sc, nl2, red, tmin, bnd, cando, cpos, selj, selp, flags, bytes;
+};
+
+__host__ __device__ inline ExLayout ex_layout(int g, int dp, int k) {
+    ExLayout L;
+    size_t o = 0;
+    L.nrow = o;  // k x dp floats: the neighbours' rows
+    o += ((sizeof(float) * (size_t)k * dp) + 15) & ~(size_t)15;
+    L.dist = o;  // g doubles
+    o += sizeof(double) * (size_t)g;
+    L.xs = o;  // dp doubles (zero beyond d)
+    o += sizeof(double) * (size_t)dp;
+    L.cdist = o;  // collected distances
+    o += sizeof(double) * EX_SEL_CAP;
+    L.seld = o;  // the k nearest: distances
+    o += sizeof(double) * ESOM_MAX_K;
+    L.sc = o;  // scores
+    o += sizeof(double) * ESOM_MAX_K;
+    L.nl2 = o;  // the neighbours' 2-D positions
+    o += sizeof(double) * 2 * ESOM_MAX_K;
+    L.red = o;  // block sums: 6 per wavefront
+    o += sizeof(double) * 6 * (EX_THREADS / 64);
+    L.tmin = o;  // the threads' minima
+    o += sizeof(double) * EX_THREADS;
+    L.bnd = o;  // bound from those minima
+    o += sizeof(double) * 2;
+    L.cando = o;  // collected landmark indices
+    o += sizeof(int) * EX_SEL_CAP;
+    L.cpos = o;  // collected landmark positions
+    o += sizeof(int) * EX_SEL_CAP;
+    L.selj = o;  // the k nearest: landmark indices
+    o += sizeof(int) * ESOM_MAX_K;
+    L.selp = o;  // the k nearest: positions
+    o += sizeof(int) * ESOM_MAX_K;
+    L.flags = o;  // [0] collected count, [1] no k finite distances
+    o += sizeof(int) * 4;
+    L.bytes = (o + 15) & ~(size_t)15;
+    return L;
+}
+
 __device__ __forceinline__ bool lex_less(double a, int ia, double b, int ib) {
     return a < b || (a == b && ia < ib);
 }
 
+// Score of a neighbour at distance dl (Section 3: the rank-weighted mean mu
+// and variance var of the k distances, the boost exponent, and the cutoff
+// factor relative to the k-th distance dlk).  Not inlined: the FP64
+// exponentials would otherwise raise the register count of the whole kernel.
+__device__ __noinline__ double exact_score(double dl, double dlk, double mu, double var, bool flat,
+                                           float boost, float cutoff, int use_cutoff) {
+    const double ev = flat ? 1.0 : exp((double)boost * (mu - dl) / sqrt(var));
+    const double cv = use_cutoff ? 1.0 - exp((double)cutoff * (dl / dlk - 1.0)) : 1.0;
+    return ev * cv;
+}
+
+// x^y, not inlined for the same reason.
+__device__ __noinline__ double exact_pow(double x, double y) { return pow(x, y); }
+
 __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_points) {
     extern __shared__ __align__(16) unsigned char esm[];
-    float *nrow = reinterpret_cast<float *>(esm);           // k x dp: the neighbours' rows
-    double *dist = reinterpret_cast<double *>(nrow + (size_t)a.k * a.dp);  // g
-    double *xs = dist + a.g;                                // dp (zero beyond d)
-    double *sel_d = xs + a.dp;                              // k
-    double *sc = sel_d + ESOM_MAX_K;                        // k
-    double *red = sc + ESOM_MAX_K;                          // 6 per wave
-    int *sel_j = reinterpret_cast<int *>(red + 6 * (EX_THREADS / 64));  // k
-    int *cand = sel_j + ESOM_MAX_K;                         // EX_SEL_CAP positions
-    int *cando = cand + EX_SEL_CAP;                         // EX_SEL_CAP landmark indices
-    int *flags = cando + EX_SEL_CAP;                        // [0] count, [1] bad
+    const int k = a.k;
+    const int g = a.g;
+    const int dq = a.dp / 4;  // float4 per row (dp is a multiple of 16)
+    const ExLayout Lo = ex_layout(g, a.dp, k);
+    float *nrow = reinterpret_cast<float *>(esm + Lo.nrow);
+    double *dist = reinterpret_cast<double *>(esm + Lo.dist);
+    double *xs = reinterpret_cast<double *>(esm + Lo.xs);
+    double *cdist = reinterpret_cast<double *>(esm + Lo.cdist);
+    double *sel_d = reinterpret_cast<double *>(esm + Lo.seld);
+    double *sc = reinterpret_cast<double *>(esm + Lo.sc);
+    double *nl2 = reinterpret_cast<double *>(esm + Lo.nl2);
+    double *red = reinterpret_cast<double *>(esm + Lo.red);
+    double *tmin = reinterpret_cast<double *>(esm + Lo.tmin);
+    double *bnd = reinterpret_cast<double *>(esm + Lo.bnd);
+    int *cando = reinterpret_cast<int *>(esm + Lo.cando);
+    int *cpos = reinterpret_cast<int *>(esm + Lo.cpos);
+    int *sel_j = reinterpret_cast<int *>(esm + Lo.selj);
+    int *sel_p = reinterpret_cast<int *>(esm + Lo.selp);
+    int *flags = reinterpret_cast<int *>(esm + Lo.flags);
     const int tid = threadIdx.x;
     const int lane = tid & 63;
     const int wv = tid >> 6;
     const long long cnt = all_points
                               ? a.n
                               : (long long)min(a.counters[C_FB_LEN], (unsigned long long)a.n);
-    const int k = a.k;
-    const int g = a.g;
     unsigned long long n_fb = 0, n_unc = 0, n_tie = 0, n_ill = 0, n_deg = 0;
+    // appends landmark position j (index o, distance s) to the collected list
+    auto collect = [&](int j, int o, double s) {
+        const int slot = atomicAdd(&flags[0], 1);
+        if (slot < EX_SEL_CAP) {
+            cdist[slot] = s;
+            cando[slot] = o;
+            cpos[slot] = j;
+        }
+    };
     for (long long e = blockIdx.x; e < cnt; e += gridDim.x) {
         const long long pi = all_points ? e : (long long)a.fb_list[e];
         const unsigned reason = all_points ? 0u : (unsigned)a.fb_reason[e];
@@ -316,43 +431,73 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
         if (tid == 0) {
             flags[0] = 0;
             flags[1] = 0;
+            bnd[0] = NAN;
         }
         __syncthreads();
         // 1. distances (LDS and rows by landmark position); collect the
         // landmarks within the bound
+        const bool use_thr = thr < INFINITY;
+        double tm = INFINITY;
         for (int j = tid; j < g; j += EX_THREADS) {
+            const int oj = a.perm[j];
             const float4 *Lj = reinterpret_cast<const float4 *>(a.Lpad + (size_t)j * a.dp);
             double s = 0.0;
-            for (int q = 0; q < a.dp / 4; ++q) {
-                const float4 v = Lj[q];
-                const double d0 = xs[4 * q] - (double)v.x, d1 = xs[4 * q + 1] - (double)v.y;
-                const double d2 = xs[4 * q + 2] - (double)v.z, d3 = xs[4 * q + 3] - (double)v.w;
-                s = fma(d0, d0, s);
-                s = fma(d1, d1, s);
-                s = fma(d2, d2, s);
-                s = fma(d3, d3, s);
-            }
-            dist[j] = s;
-            if (s <= thr) {
-                const int slot = atomicAdd(&flags[0], 1);
-                if (slot < EX_SEL_CAP) {
-                    cand[slot] = j;
-                    cando[slot] = a.perm[j];
+            for (int q = 0; q < dq; q += 4) {
+                float4 v[4];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) v[u] = Lj[q + u];
+#pragma unroll
+                for (int u = 0; u < 4; ++u) {
+                    const double *xq = xs + 4 * (q + u);
+                    const double d0 = xq[0] - (double)v[u].x, d1 = xq[1] - (double)v[u].y;
+                    const double d2 = xq[2] - (double)v[u].z, d3 = xq[3] - (double)v[u].w;
+                    s = fma(d0, d0, s);
+                    s = fma(d1, d1, s);
+                    s = fma(d2, d2, s);
+                    s = fma(d3, d3, s);
                 }
             }
+            dist[j] = s;
+            tm = fmin(tm, s);
+            if (use_thr && s <= thr) collect(j, oj, s);
         }
         __syncthreads();
-        // 2. the k nearest, sorted by (distance, index)
-        const int nc = flags[0];
+        int nc = flags[0];
+        // 2. no usable bound: the k-th smallest of the threads' minima (by
+        // value, then thread) bounds the k-th distance; g >= k landmarks
+        // spread over the threads give at least k finite minima
+        if (!(nc >= k && nc <= EX_SEL_CAP)) {
+            tmin[tid] = tm;
+            __syncthreads();
+            if (tid == 0) flags[0] = 0;
+            int rank = 0;
+#pragma unroll 8
+            for (int o = 0; o < EX_THREADS; ++o) {
+                const double v = tmin[o];
+                rank += (v < tm || (v == tm && o < tid)) ? 1 : 0;
+            }
+            if (rank == k - 1) bnd[0] = tm;
+            __syncthreads();
+            const double b = bnd[0];  // NaN when distances are not finite: nothing collected
+            for (int j = tid; j < g; j += EX_THREADS) {
+                const double s = dist[j];
+                if (s <= b) collect(j, a.perm[j], s);
+            }
+            __syncthreads();
+            nc = flags[0];
+        }
+        // 3. the k nearest, sorted by (distance, index)
         if (nc >= k && nc <= EX_SEL_CAP) {
             for (int c = tid; c < nc; c += EX_THREADS) {
-                const double dc = dist[cand[c]];
+                const double dc = cdist[c];
                 const int jc = cando[c];
                 int rank = 0;
-                for (int o = 0; o < nc; ++o) rank += lex_less(dist[cand[o]], cando[o], dc, jc) ? 1 : 0;
+#pragma unroll 4
+                for (int o = 0; o < nc; ++o) rank += lex_less(cdist[o], cando[o], dc, jc) ? 1 : 0;
                 if (rank < k) {
                     sel_d[rank] = dc;
                     sel_j[rank] = jc;
+                    sel_p[rank] = cpos[c];
                 }
             }
         } else if (wv == 0) {
@@ -382,6 +527,7 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
                 if (lane == 0) {
                     sel_d[r] = bv;
                     sel_j[r] = bj;
+                    sel_p[r] = bp;
                     if (bj != 0x7fffffff)
                         dist[bp] = NAN;
                     else
@@ -414,30 +560,28 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
             __syncthreads();
             continue;
         }
-        // 3. scores (wave 0, one neighbour per lane; k <= 64)
+        // 4. scores (wavefront 0, one neighbour per lane; k <= 64)
         const bool degenerate = sqrt(sel_d[0]) == sqrt(sel_d[k - 1]);  // all delta equal
         if (wv == 0) {
-            const double dq = lane < k ? sqrt(sel_d[lane]) : 0.0;
+            const double dl = lane < k ? sqrt(sel_d[lane]) : 0.0;
             const double wq = lane < k ? 1.0 / (lane + 1) : 0.0;
             const double W = wave_sum(wq);
-            const double mu = wave_sum(wq * dq) / W;
-            const double var = wave_sum(lane < k ? wq * (dq - mu) * (dq - mu) : 0.0) / W;
+            const double mu = wave_sum(wq * dl) / W;
+            const double var = wave_sum(lane < k ? wq * (dl - mu) * (dl - mu) : 0.0) / W;
             const bool flat = !(var > 1e-30 * mu * mu);
-            if (lane < k) {
-                const double dlk = sqrt(sel_d[k - 1]);
-                const double ev = flat ? 1.0 : exp((double)a.boost * (mu - dq) / sqrt(var));
-                const double cv = a.use_cutoff ? 1.0 - exp((double)a.cutoff * (dq / dlk - 1.0)) : 1.0;
-                sc[lane] = degenerate ? 0.0 : ev * cv;
-            }
+            if (lane < k)
+                sc[lane] = degenerate ? 0.0
+                                      : exact_score(dl, sqrt(sel_d[k - 1]), mu, var, flat, a.boost,
+                                                    a.cutoff, a.use_cutoff);
         }
-        __syncthreads();
-        // the neighbours' rows into LDS (coalesced), then every pair's
+        // the neighbours' rows and 2-D positions into LDS, then every pair's
         // projection from them, spread over the threads
-        for (int e = tid; e < k * (a.dp / 4); e += EX_THREADS) {
-            const int q = e / (a.dp / 4), c = e % (a.dp / 4);
+        for (int e2 = tid; e2 < k * dq; e2 += EX_THREADS) {
+            const int q = e2 / dq, c = e2 % dq;
             reinterpret_cast<float4 *>(nrow + (size_t)q * a.dp)[c] =
-                reinterpret_cast<const float4 *>(a.Lpad + (size_t)a.ipos[sel_j[q]] * a.dp)[c];
+                reinterpret_cast<const float4 *>(a.Lpad + (size_t)sel_p[q] * a.dp)[c];
         }
+        if (tid < 2 * k) nl2[tid] = a.l2d[2 * sel_j[tid >> 1] + (tid & 1)];
         __syncthreads();
         double M00 = 0.0, M01 = 0.0, M11 = 0.0, r0 = 0.0, r1 = 0.0, ssum = 0.0;
         const int npair = k * (k - 1) / 2;
@@ -448,22 +592,31 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
                 ++qi;
             }
             const int qj = qi + 1 + rem;
-            const int u = sel_j[qi], v = sel_j[qj];
-            const float *Lu = nrow + (size_t)qi * a.dp;
-            const float *Lv = nrow + (size_t)qj * a.dp;
+            const float4 *Lu = reinterpret_cast<const float4 *>(nrow + (size_t)qi * a.dp);
+            const float4 *Lv = reinterpret_cast<const float4 *>(nrow + (size_t)qj * a.dp);
+            // padded dimensions are 0 in the rows and in xs
             double HH = 0.0, xH = 0.0;
-            for (int q = 0; q < a.d; ++q) {
-                const double H = (double)Lv[q] - (double)Lu[q];
-                HH = fma(H, H, HH);
-                xH = fma(xs[q] - (double)Lu[q], H, xH);
+            for (int q = 0; q < dq; ++q) {
+                const float4 lu = Lu[q], lv = Lv[q];
+                const double *xq = xs + 4 * q;
+                const double H0 = (double)lv.x - (double)lu.x, H1 = (double)lv.y - (double)lu.y;
+                const double H2 = (double)lv.z - (double)lu.z, H3 = (double)lv.w - (double)lu.w;
+                HH = fma(H0, H0, HH);
+                HH = fma(H1, H1, HH);
+                HH = fma(H2, H2, HH);
+                HH = fma(H3, H3, HH);
+                xH = fma(xq[0] - (double)lu.x, H0, xH);
+                xH = fma(xq[1] - (double)lu.y, H1, xH);
+                xH = fma(xq[2] - (double)lu.z, H2, xH);
+                xH = fma(xq[3] - (double)lu.w, H3, xH);
             }
             if (HH == 0.0) continue;
             const double D = xH / HH;
-            const double lux = a.l2d[2 * u], luy = a.l2d[2 * u + 1];
-            const double hx = (double)a.l2d[2 * v] - lux, hy = (double)a.l2d[2 * v + 1] - luy;
+            const double lux = nl2[2 * qi], luy = nl2[2 * qi + 1];
+            const double hx = nl2[2 * qj] - lux, hy = nl2[2 * qj + 1] - luy;
             const double hh = hx * hx + hy * hy;
             if (hh == 0.0) continue;
-            const double qw = sc[qi] * sc[qj] * (a.adjust == 1.0f ? 1.0 / hh : pow(hh, -(double)a.adjust));
+            const double qw = sc[qi] * sc[qj] * (a.adjust == 1.0f ? 1.0 / hh : exact_pow(hh, -(double)a.adjust));
             const double rhs = D + (hx * lux + hy * luy) / hh;
             M00 += qw * hx * hx / hh;
             M01 += qw * hx * hy / hh;
@@ -475,8 +628,8 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
             const double gs = (double)a.gravity * sc[tid];
             M00 += gs;
             M11 += gs;
-            r0 += gs * a.l2d[2 * sel_j[tid]];
-            r1 += gs * a.l2d[2 * sel_j[tid] + 1];
+            r0 += gs * nl2[2 * tid];
+            r1 += gs * nl2[2 * tid + 1];
             ssum += sc[tid];
         }
         M00 = wave_sum(M00);
@@ -494,7 +647,7 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
             red[6 * wv + 5] = ssum;
         }
         __syncthreads();
-        // 4. solve
+        // 5. solve
         if (tid == 0) {
             double t[6] = {0.0, 0.0, 0.0, 0.0, 0.0, 0.0};
             for (int w = 0; w < EX_THREADS / 64; ++w)
@@ -504,8 +657,8 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
             if (degenerate || !(t[5] > 0.0) || !(det > 0.0)) {
                 double cx = 0.0, cy = 0.0;
                 for (int q = 0; q < k; ++q) {
-                    cx += a.l2d[2 * sel_j[q]];
-                    cy += a.l2d[2 * sel_j[q] + 1];
+                    cx += nl2[2 * q];
+                    cy += nl2[2 * q + 1];
                 }
                 px = cx / k;
                 py = cy / k;
@@ -528,22 +681,21 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
     }
 }
 
-static size_t exact_smem(const EmbedArgs &a) {
-    return sizeof(double) * ((size_t)a.g + a.dp + 2 * ESOM_MAX_K + 6 * (EX_THREADS / 64)) +
-           sizeof(int) * (ESOM_MAX_K + 2 * EX_SEL_CAP + 4) + sizeof(float) * (size_t)a.k * a.dp;
-}
-
-hipError_t launch_fallback(const EmbedArgs &a, int num_cus, hipStream_t s) {
+hipError_t launch_fallback(const EmbedArgs &a, int num_cus, size_t lds_per_block, hipStream_t s) {
     // The list length is only known on the device: a fixed grid loops over it.
-    hipLaunchKernelGGL(embed_exact, dim3(num_cus * 2), dim3(EX_THREADS), exact_smem(a), s, a, 0);
+    const size_t smem = ex_layout(a.g, a.dp, a.k).bytes;
+    if (smem > lds_per_block) return hipErrorInvalidValue;
+    hipLaunchKernelGGL(embed_exact, dim3(num_cus * 4), dim3(EX_THREADS), smem, s, a, 0);
     return hipGetLastError();
 }
 
-hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, hipStream_t s) {
+hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, size_t lds_per_block, hipStream_t s) {
+    const size_t smem = ex_layout(a.g, a.dp, a.k).bytes;
+    if (smem > lds_per_block) return hipErrorInvalidValue;
     long long blocks = a.n;
-    if (blocks > (long long)num_cus * 8) blocks = (long long)num_cus * 8;
+    if (blocks > (long long)num_cus * 4) blocks = (long long)num_cus * 4;
     if (blocks < 1) blocks = 1;
-    hipLaunchKernelGGL(embed_exact, dim3((unsigned)blocks), dim3(EX_THREADS), exact_smem(a), s, a, 1);
+    hipLaunchKernelGGL(embed_exact, dim3((unsigned)blocks), dim3(EX_THREADS), smem, s, a, 1);
     return hipGetLastError();
 }
 

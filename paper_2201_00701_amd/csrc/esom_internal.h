@@ -43,8 +43,8 @@ struct Prep {
     void *A = nullptr;       // MFMA landmark operand, -2 (L - c), tile layout
     float *norms = nullptr;  // ntiles * 32: |L_j - c|^2 in MFMA row order
     float *Lpad = nullptr;   // g * dp:  L rows padded with zeros to dp
-    float *inv2 = nullptr;   // g * g:   1 / (2 |L_u - L_v|^2), -1 if zero
-    float *lmax = nullptr;   // 1:       max_j |L_j - c|
+    float2 *pairs = nullptr;  // g * g: (1 / (2 |L_u - L_v|^2), 1 / |l_v - l_u|^2), (0, 0) if skipped
+    float *lmax = nullptr;   // 2:       max_j |L_j - c|, max_j |BF16(-2 (L_j - c)) + 2 (L_j - c)|
     // Landmark order of the screen tiles, rows and pair table: position ->
     // landmark (perm) and landmark -> position (ipos).  Landmarks that are
     // close in the input space get nearby positions (see prep_order).
@@ -72,7 +72,8 @@ struct EmbedArgs {
     int64_t n, ldx;
     int d, dp, g, ntiles, npair_tiles;
     const void *A;
-    const float *norms, *cent, *Lpad, *l2d, *inv2, *lmax;
+    const float *norms, *cent, *Lpad, *l2d, *lmax;
+    const float2 *pairs;
     const int32_t *perm, *ipos;  // position -> landmark, landmark -> position
     int k, kact, jsel;  // kact: neighbours with non-zero score; jsel: per-lane order statistic
     int use_cutoff;
@@ -97,14 +98,14 @@ struct EmbedArgs {
     uint8_t *knn_mark;
 };
 
-// Launchers (esom_embed.hip).
-hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long long *counters,
+// Launchers (esom_core.hip).
+hipError_t launch_prep(const Prep &P, const float *L, const float *l2d, int mode, unsigned long long *counters,
                        long long n_points, hipStream_t s);
 hipError_t launch_embed(const EmbedArgs &a, int mode, int kp, int num_cus, size_t lds_per_block,
                         hipStream_t s);
-hipError_t launch_fallback(const EmbedArgs &a, int num_cus, hipStream_t s);
+hipError_t launch_fallback(const EmbedArgs &a, int num_cus, size_t lds_per_block, hipStream_t s);
 hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s);
-hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, hipStream_t s);
+hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, size_t lds_per_block, hipStream_t s);
 
 // Landmark update (esom_update.hip).
 struct UpdateArgs {

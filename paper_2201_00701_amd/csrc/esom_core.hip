@@ -96,10 +96,14 @@ __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
     }
 }
 
-// One block: the pivot chain, then the landmarks ranked by (chain place of
-// their pivot, distance to it, index) as 64-bit keys (each thread counts the
-// smaller keys of its landmark).  Writes perm (position -> landmark) and ipos
-// (landmark -> position).
+// One block orders the landmarks:
+//  1. the pivot chain (pivot-to-pivot squared distances from the assignment
+//     pass); a pivot's place is its step in the chain;
+//  2. each landmark's key (place of its pivot, distance to it, index), 64 bits;
+//  3. a counting sort by place (a histogram and its prefix sum), then each
+//     landmark's position within its place by counting the smaller keys of
+//     the same place only (about g / 64 of them).
+// Writes perm (position -> landmark) and ipos (landmark -> position).
 __global__ void __launch_bounds__(1024) prep_order(int g, const int *__restrict__ pcl,
                                                    const float *__restrict__ pdist,
                                                    const float *__restrict__ ppg,
@@ -108,12 +112,19 @@ __global__ void __launch_bounds__(1024) prep_order(int g, const int *__restrict_
     const int P = order_pivots(g);
     unsigned long long *key = reinterpret_cast<unsigned long long *>(osm);  // g
     float *pp = reinterpret_cast<float *>(key + g);                          // P x P
-    int *place = reinterpret_cast<int *>(pp + ORDER_MAX_P * ORDER_MAX_P);   // P
+    int *place = reinterpret_cast<int *>(pp + ORDER_MAX_P * ORDER_MAX_P);    // P
+    int *cnt = place + ORDER_MAX_P;                                          // landmarks per place
+    int *start = cnt + ORDER_MAX_P;                                          // first position of a place
+    int *fill = start + ORDER_MAX_P;                                         // bucket fill counters
+    int *bucket = fill + ORDER_MAX_P;                                        // g: landmarks by place
     const int tid = threadIdx.x;
-    // pivot-to-pivot squared distances (from the assignment pass)
     for (int e = tid; e < P * P; e += blockDim.x) pp[e] = ppg[e];
+    if (tid < ORDER_MAX_P) {
+        cnt[tid] = 0;
+        fill[tid] = 0;
+    }
     __syncthreads();
-    // greedy chain over the pivots (one wavefront, lane = pivot): each step
+    // 1. greedy chain over the pivots (one wavefront, lane = pivot): each step
     // takes the nearest pivot not yet taken, by a wave minimum of 32-bit keys
     // (distance bits with the 6 low bits replaced by the pivot number)
     if (tid < 64) {
@@ -129,19 +140,38 @@ __global__ void __launch_bounds__(1024) prep_order(int g, const int *__restrict_
         }
     }
     __syncthreads();
-    // keys: place (6 bits) | distance bits (31) | index (13)
+    // 2. keys: place (6 bits) | distance bits (31) | index (13); landmarks per place
     for (int j = tid; j < g; j += blockDim.x) {
+        const int pl = place[pcl[j]];
         const unsigned db = __float_as_uint(fmaxf(pdist[j], 0.f)) & 0x7fffffffu;
-        key[j] = ((unsigned long long)place[pcl[j]] << 44) | ((unsigned long long)db << 13) |
-                 (unsigned long long)j;
+        key[j] = ((unsigned long long)pl << 44) | ((unsigned long long)db << 13) | (unsigned long long)j;
+        atomicAdd(&cnt[pl], 1);
     }
     __syncthreads();
-    // position of each landmark = number of smaller keys (keys are distinct)
+    if (tid < 64) {
+        // exclusive prefix sum over the places (P <= 64)
+        int v = tid < P ? cnt[tid] : 0;
+        int incl = v;
+#pragma unroll
+        for (int o = 1; o < 64; o <<= 1) {
+            const int t = __shfl_up(incl, o);
+            if (tid >= o) incl += t;
+        }
+        if (tid < P) start[tid] = incl - v;
+    }
+    __syncthreads();
+    // 3. buckets, then the rank within the bucket (keys are distinct)
+    for (int j = tid; j < g; j += blockDim.x) {
+        const int pl = (int)(key[j] >> 44);
+        bucket[start[pl] + atomicAdd(&fill[pl], 1)] = j;
+    }
+    __syncthreads();
     for (int j = tid; j < g; j += blockDim.x) {
         const unsigned long long kj = key[j];
-        int pos = 0;
-#pragma unroll 8
-        for (int i = 0; i < g; ++i) pos += key[i] < kj ? 1 : 0;
+        const int pl = (int)(kj >> 44);
+        const int b0 = start[pl], nb = cnt[pl];
+        int pos = b0;
+        for (int i = 0; i < nb; ++i) pos += key[bucket[b0 + i]] < kj ? 1 : 0;
         perm[pos] = j;
         ipos[j] = pos;
     }
@@ -225,14 +255,14 @@ __device__ __forceinline__ void prep_pairs(int blk, float *prs, const float *__r
     const int rs = d + 1;
     float *Lu = prs, *Lv = prs + PAIR_TILE * rs;
     float2 *lu2 = reinterpret_cast<float2 *>(prs + 2 * PAIR_TILE * rs);  // 2 PAIR_TILE rs is even
+    if (l2d && threadIdx.x < 2 * PAIR_TILE) {
+        const int r = threadIdx.x % PAIR_TILE, w = (threadIdx.x < PAIR_TILE ? u0 : v0) + r;
+        lu2[threadIdx.x] = w < g ? reinterpret_cast<const float2 *>(l2d)[perm[w]] : make_float2(0.f, 0.f);
+    }
     for (int e = threadIdx.x; e < PAIR_TILE * d; e += blockDim.x) {
         const int r = e / d, q = e % d;
         Lu[r * rs + q] = u0 + r < g ? L[(size_t)perm[u0 + r] * d + q] : 0.f;
         Lv[r * rs + q] = v0 + r < g ? L[(size_t)perm[v0 + r] * d + q] : 0.f;
-    }
-    if (l2d && threadIdx.x < 2 * PAIR_TILE) {
-        const int r = threadIdx.x % PAIR_TILE, w = (threadIdx.x < PAIR_TILE ? u0 : v0) + r;
-        lu2[threadIdx.x] = w < g ? reinterpret_cast<const float2 *>(l2d)[perm[w]] : make_float2(0.f, 0.f);
     }
     __syncthreads();
     const int ty = threadIdx.x / PAIR_TILE, tx = threadIdx.x % PAIR_TILE;
@@ -250,9 +280,10 @@ __device__ __forceinline__ void prep_pairs(int blk, float *prs, const float *__r
         const float2 lu = lu2[ty], lv = lu2[PAIR_TILE + tx];
         const double hx = (double)lv.x - (double)lu.x, hy = (double)lv.y - (double)lu.y;
         const double hh = fma(hx, hx, hy * hy);
+        // FP32 reciprocals (about 1 ulp): the fast kernel uses both in FP32
         if (hh > 0.0) {
-            iv = (float)(0.5 / s);
-            w = (float)(1.0 / hh);
+            iv = 0.5f * __builtin_amdgcn_rcpf((float)s);
+            w = __builtin_amdgcn_rcpf((float)hh);
         }
     }
     pairs[(size_t)u * g + v] = make_float2(iv, w);
@@ -279,7 +310,7 @@ hipError_t launch_prep(const Prep &P, const float *L, const float *l2d, int mode
                        dim3(256), sizeof(float) * P.d * 64, s, L, P.g, P.d, P.dp, P.cent, P.lmax, counters,
                        n_points, P.pcl, P.pdist, P.ppiv);
     const size_t osm = sizeof(unsigned long long) * P.g + sizeof(float) * ORDER_MAX_P * ORDER_MAX_P +
-                       sizeof(int) * ORDER_MAX_P;
+                       sizeof(int) * (4 * ORDER_MAX_P + P.g);
     hipLaunchKernelGGL(prep_order, dim3(1), dim3(1024), osm, s, P.g, P.pcl, P.pdist, P.ppiv, P.perm,
                        P.ipos);
     const int gpad = P.ntiles * TILE;

@@ -174,6 +174,22 @@ __device__ __forceinline__ int select_jth(int (&lo)[16], int (&hi)[16], int j) {
     return t;
 }
 
+// FP32 minimum as a single instruction: the median of (a, b, ninf) with ninf
+// = -inf.  fminf, or a median with a visible -inf constant (which the
+// compiler turns into fminf), quiets both operands with an extra instruction
+// each.  (Not inline assembly: the compiler must see the read of an MFMA
+// result to insert the wait states it needs.)
+__device__ __forceinline__ float vmin32(float a, float b, float ninf) {
+    return __builtin_amdgcn_fmed3f(a, b, ninf);
+}
+
+// -inf in a scalar register, opaque to the compiler.
+__device__ __forceinline__ float opaque_neg_inf() {
+    float r;
+    asm volatile("s_mov_b32 %0, 0xff800000" : "=s"(r));
+    return r;
+}
+
 // FP64 minimum / maximum as single instructions.  fmin/fmax would add a
 // quieting step per operand for signalling NaNs, which never occur here (the
 // operands are packed keys built by integer operations, or +inf).
@@ -658,21 +674,30 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             dxp[p] = (MODE == 1) ? dpart + __shfl_xor(dpart, 32) : 0.f;
         }
 
-        // ---------------- pass 1: group minima of the approximate squared distances
-        // key + |x - c|^2 (bit patterns: integer minima, no NaN quieting).
-        int gmin[2][2][16];
+        // ---------------- pass 1: group minima of the keys.  BF16 mode adds
+        // |x - c|^2 once per group afterwards (rounding is monotone, so the
+        // minimum of the sums equals the sum with the minimum) and takes FP32
+        // minima; FP32 mode, where this measured slower, adds it per key and
+        // takes integer minima of the bit patterns of key + |x - c|^2.
+        float gmin[2][2][16];
 #pragma unroll
         for (int p = 0; p < 2; ++p)
 #pragma unroll
             for (int q = 0; q < 2; ++q)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) gmin[p][q][r] = 0x7F800000;
+                for (int r = 0; r < 16; ++r) gmin[p][q][r] = INFINITY;
+        const float ninf = opaque_neg_inf();
         auto pass1_consume = [&](const f32x16 (&acc)[2], int half) {
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int r = 0; r < 16; ++r)
-                    gmin[p][half][r] = min(gmin[p][half][r], __float_as_int(acc[p][r] + xnp[p]));
+                for (int r = 0; r < 16; ++r) {
+                    if constexpr (MODE == 1)
+                        gmin[p][half][r] = vmin32(gmin[p][half][r], acc[p][r], ninf);
+                    else
+                        gmin[p][half][r] = __int_as_float(
+                            min(__float_as_int(gmin[p][half][r]), __float_as_int(acc[p][r] + xnp[p])));
+                }
         };
         {
             TileRegs<MODE, DC> T;
@@ -697,8 +722,10 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             int v0[16], v1[16];
 #pragma unroll
             for (int r = 0; r < 16; ++r) {
-                v0[r] = max(gmin[p][0][r], 0);
-                v1[r] = max(gmin[p][1][r], 0);
+                // approximate delta^2 as bit patterns; negative values (rounding)
+                // become 0, and integer order is then float order
+                v0[r] = max(__float_as_int(MODE == 1 ? gmin[p][0][r] + xnp[p] : gmin[p][0][r]), 0);
+                v1[r] = max(__float_as_int(MODE == 1 ? gmin[p][1][r] + xnp[p] : gmin[p][1][r]), 0);
             }
             int tl = select_jth(v0, v1, a.jsel);
             tl = min(tl, 0x7F7FFFFF);  // +inf (too few landmarks) -> FLT_MAX

@@ -239,7 +239,8 @@ __device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict_
 // projection of a point onto the segment between two landmarks) and the
 // inverse squared 2-D segment length, both from FP64 differences and both 0
 // for a skipped pair; indexed by landmark positions.  Each entry depends only
-// on the two landmarks, so the per-point pair loop needs no division.  A
+// on the two landmarks, so the per-point pair loop needs no division; the
+// table is exactly symmetric (the same FP64 sums either way).  A
 // 256-thread block computes a 16 x 16 tile of pairs from the two
 // 16-row slices of L staged in LDS (row stride d + 1 floats: no bank
 // conflicts between the 16 rows a wave reads); rows are read and the table

@@ -217,22 +217,16 @@ __device__ __forceinline__ void insert_sorted(double (&s)[KP], double &rej, doub
     rej = vmin64(rej, v);
 }
 
-// Next non-empty bitmap word of a lane: masks mk0 / mk1 of the words of the
-// two screen halves (bit tp = tile pair tp); row = the lane's words, stride 64
-// per tile pair, +32 for the second half.  nb = 0 when none is left.
-__device__ __forceinline__ void next_word(unsigned long long &mk0, unsigned long long &mk1,
-                                          const unsigned *row, unsigned &nb, int &nhh, int &ntp) {
-    nb = 0u;
-    if (mk0) {
-        nhh = 0;
-        ntp = __builtin_ctzll(mk0);
-        mk0 &= mk0 - 1ull;
-        nb = row[ntp * 64];
-    } else if (mk1) {
-        nhh = 1;
-        ntp = __builtin_ctzll(mk1);
-        mk1 &= mk1 - 1ull;
-        nb = row[ntp * 64 + 32];
+// Next non-empty 64-bit bitmap word of a point: mk marks the non-empty words
+// (bit tp = tile pair tp), row = the point's words, stride 32 per tile pair.
+// nb = 0 when none is left.
+__device__ __forceinline__ void next_word(unsigned long long &mk, const unsigned long long *row,
+                                          unsigned long long &nb, int &ntp) {
+    nb = 0ull;
+    if (mk) {
+        ntp = __builtin_ctzll(mk);
+        mk &= mk - 1ull;
+        nb = row[ntp * 32];
     }
 }
 
@@ -744,7 +738,9 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
 
         // ---------------- pass 2: candidate bitmaps (key <= tau) into LDS.  The
         // sign of tau - key is shifted in (1 = not a candidate) and the word
-        // complemented; a mask per lane marks the non-empty words.
+        // complemented.  The two screen halves' words of a point and tile pair
+        // sit side by side, bit-reversed, as one 64-bit word: bit 32 h + b is
+        // position 64 tp + 2 b + h.  A mask per point marks the non-empty words.
         unsigned long long nonempty[2] = {0ull, 0ull};
         {
             unsigned word[2] = {0u, 0u};
@@ -759,7 +755,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
 #pragma unroll
                 for (int p = 0; p < 2; ++p) {
                     const unsigned wd = ~word[p];
-                    bitsL[(p * W + tp) * 64 + lane] = wd;
+                    bitsL[((p * W + tp) * 32 + i32) * 2 + h] = __builtin_bitreverse32(wd);
                     nonempty[p] |= (unsigned long long)(wd != 0u) << tp;
                 }
             };
@@ -802,9 +798,12 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 certL[32 * p + i32] = (tc >= FLT_MAX) ? INFINITY : rhs;
             }
         }
-        // masks of lane (screen half h, point i32) for point groups p = 0, 1
-        maskL[(0 * 2 + h) * 32 + i32] = nonempty[0];
-        maskL[(1 * 2 + h) * 32 + i32] = nonempty[1];
+        // masks of the points (p, i32): either screen half's word non-empty
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const unsigned long long both = nonempty[p] | __shfl_xor(nonempty[p], 32);
+            if (h == 0) maskL[32 * p + i32] = both;
+        }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
@@ -839,30 +838,29 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             // Each lane walks its own candidates across all its words (one
             // candidate per iteration), so the wave iterates max_l m_l times.
             // The next non-empty word is read one word ahead.
-            unsigned long long mk0 = valid ? maskL[(h * 2 + 0) * 32 + i32] : 0ull;
-            unsigned long long mk1 = valid ? maskL[(h * 2 + 1) * 32 + i32] : 0ull;
-            int nhh = 0, ntp = 0;
-            unsigned nb = 0u;
-            next_word(mk0, mk1, bitsL + h * W * 64 + i32, nb, nhh, ntp);
-            unsigned b = 0u;
-            int chh = 0, ctp = 0;
+            unsigned long long mk = valid ? maskL[lane] : 0ull;
+            const unsigned long long *row = reinterpret_cast<const unsigned long long *>(bitsL) + h * W * 32 + i32;
+            int ntp = 0;
+            unsigned long long nb = 0ull;
+            next_word(mk, row, nb, ntp);
+            unsigned long long b = 0ull;
+            int ctp = 0;
             // The loop is wave-uniform (it ends when no lane has a candidate
             // left); a lane without one rescores landmark 0 and inserts +inf,
             // which leaves its list unchanged.  Keeping the insertion out of
             // divergent control flow keeps the list in place in registers.
             for (;;) {
-                if (b == 0u && nb != 0u) {
+                if (b == 0ull && nb != 0ull) {
                     b = nb;
-                    chh = nhh;
                     ctp = ntp;
-                    next_word(mk0, mk1, bitsL + h * W * 64 + i32, nb, nhh, ntp);
+                    next_word(mk, row, nb, ntp);
                 }
-                const bool act = b != 0u;
+                const bool act = b != 0ull;
                 if (__ballot(act) == 0ull) break;
-                const int pos = __clz((int)b);
-                b &= ~(0x80000000u >> pos);
-                // bit pos of a word of tile pair ctp, screen half chh
-                const int j = act ? 64 * ctp + 2 * pos + chh : 0;
+                const int bit = __builtin_ctzll(b);
+                b &= b - 1ull;
+                // bit 32 h + pos of a word of tile pair ctp: position 64 ctp + 2 pos + h
+                const int j = act ? 64 * ctp + 2 * (bit & 31) + (bit >> 5) : 0;
                 float acc = 0.f;
                 if (a.lds_rows) {
                     const float4 *Lr = reinterpret_cast<const float4 *>(rowsL + (size_t)j * RS);

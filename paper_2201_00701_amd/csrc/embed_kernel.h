@@ -242,6 +242,15 @@ constexpr int CENT_LDS_BYTES = 512;
 // landmark -> position, 16-bit each, two halves of equal size).
 __host__ __device__ inline size_t order_lds_bytes(int g) { return (size_t)(((2 * g + 255) / 256) * 256) * 2; }
 
+// Bytes of the screen's A operand (ntiles tiles of 32 landmarks) and of its
+// LDS copy with the norms (16 per lane half and tile), 256-byte aligned.
+__host__ __device__ inline size_t tile_a_bytes(int mode, int ntiles, int dc) {
+    return (size_t)ntiles * dc * 64 * (mode == 1 ? 16 : 32);
+}
+__host__ __device__ inline size_t tile_lds_bytes(int mode, int ntiles, int dc) {
+    return (tile_a_bytes(mode, ntiles, dc) + (size_t)ntiles * 128 + 255) & ~(size_t)255;
+}
+
 // Bytes of LDS one wave needs: candidate bitmaps (2 W words per lane), or for
 // KP > 16 the neighbour staging of the pair loop in the same space; then
 // thresholds, norms and the per-lane masks of non-empty bitmap words.
@@ -275,14 +284,17 @@ struct TileRegs<0, DC> {
     float a[8 * DC];
 };
 
+// The A operand and the norms come from Abase / Nbase: global memory, or the
+// block's LDS copy (the caller's choice, fixed per instantiation so that the
+// compiler sees the address space).
 template <int MODE, int DC>
-__device__ __forceinline__ void load_tile(const EmbedArgs &a, int t, int lane, TileRegs<MODE, DC> &T) {
+__device__ __forceinline__ void load_tile(const void *Abase, int t, int lane, TileRegs<MODE, DC> &T) {
     if constexpr (MODE == 1) {
-        const u32x4 *Ap = reinterpret_cast<const u32x4 *>(a.A) + (size_t)t * DC * 64 + lane;
+        const u32x4 *Ap = reinterpret_cast<const u32x4 *>(Abase) + (size_t)t * DC * 64 + lane;
 #pragma unroll
         for (int c = 0; c < DC; ++c) T.a[c] = Ap[c * 64];
     } else {
-        const float *Ap = reinterpret_cast<const float *>(a.A) + (size_t)t * (8 * DC) * 64 + lane;
+        const float *Ap = reinterpret_cast<const float *>(Abase) + (size_t)t * (8 * DC) * 64 + lane;
 #pragma unroll
         for (int s = 0; s < 8 * DC; ++s) T.a[s] = Ap[s * 64];
     }
@@ -290,11 +302,11 @@ __device__ __forceinline__ void load_tile(const EmbedArgs &a, int t, int lane, T
 
 // Keys of tile t for both 32-point halves of the wave: acc[p] = |L|^2 + A B_p.
 template <int MODE, int DC>
-__device__ __forceinline__ void screen_tile(const EmbedArgs &a, int t, int lane, const TileRegs<MODE, DC> &T,
+__device__ __forceinline__ void screen_tile(const float *Nbase, int t, int lane, const TileRegs<MODE, DC> &T,
                                             const PointOperand<MODE, DC> &P, f32x16 (&acc)[2]) {
     f32x16 nrm;
     {
-        const float4 *np = reinterpret_cast<const float4 *>(a.norms + (size_t)(t * 2 + (lane >> 5)) * 16);
+        const float4 *np = reinterpret_cast<const float4 *>(Nbase + (size_t)(t * 2 + (lane >> 5)) * 16);
 #pragma unroll
         for (int i = 0; i < 4; ++i) {
             const float4 n = np[i];
@@ -586,6 +598,12 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
     unsigned short *iposL = permL + tab_bytes / 4;
     float *rowsL = reinterpret_cast<float *>(smem + CENT_LDS_BYTES + tab_bytes);
     const size_t rows_bytes = a.lds_rows ? (((size_t)a.g * RS * 4 + 255) & ~(size_t)255) : 0;
+    // optionally the screen operands (A tiles and norms), read by every wave
+    // twice per 64 points
+    const size_t a_bytes = tile_a_bytes(MODE, a.ntiles, DC);
+    const size_t tiles_bytes = a.lds_tiles ? tile_lds_bytes(MODE, a.ntiles, DC) : 0;
+    unsigned char *tilesL = smem + CENT_LDS_BYTES + tab_bytes + rows_bytes;
+    const float *normsL = reinterpret_cast<const float *>(tilesL + a_bytes);
     for (int e = threadIdx.x; e < DP; e += blockDim.x) centL[e] = e < a.d ? a.cent[e] : 0.f;
     for (int e = threadIdx.x; e < a.g; e += blockDim.x) {
         permL[e] = (unsigned short)a.perm[e];
@@ -598,8 +616,16 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 reinterpret_cast<const float4 *>(a.Lpad + (size_t)j * DP)[q];
         }
     }
+    if (a.lds_tiles) {
+        const size_t nv = (a_bytes + (size_t)a.ntiles * 128) / 16;
+        const float4 *srcA = reinterpret_cast<const float4 *>(a.A);
+        const float4 *srcN = reinterpret_cast<const float4 *>(a.norms);
+        for (size_t e = threadIdx.x; e < nv; e += blockDim.x)
+            reinterpret_cast<float4 *>(tilesL)[e] = e < a_bytes / 16 ? srcA[e] : srcN[e - a_bytes / 16];
+    }
     __syncthreads();
-    unsigned char *wsm = smem + CENT_LDS_BYTES + tab_bytes + rows_bytes + (size_t)wave * wave_smem_bytes(KP, W);
+    unsigned char *wsm = smem + CENT_LDS_BYTES + tab_bytes + rows_bytes + tiles_bytes +
+                         (size_t)wave * wave_smem_bytes(KP, W);
     unsigned *bitsL = reinterpret_cast<unsigned *>(wsm);
     float *nbD2 = reinterpret_cast<float *>(wsm);
     float *nbS = nbD2 + KP * 64;
@@ -699,17 +725,28 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                             min(__float_as_int(gmin[p][half][r]), __float_as_int(acc[p][r] + xnp[p])));
                 }
         };
-        {
+        // one screen pass over all tiles, operands from LDS or global memory
+        auto screen_pass = [&](auto in_lds, auto consume, auto store) {
+            const void *Ab = decltype(in_lds)::value ? static_cast<const void *>(tilesL) : a.A;
+            const float *Nb = decltype(in_lds)::value ? normsL : a.norms;
             TileRegs<MODE, DC> T;
             for (int tp = 0; tp < W; ++tp) {
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
                     f32x16 acc[2];
-                    load_tile<MODE, DC>(a, 2 * tp + half, lane, T);
-                    screen_tile<MODE, DC>(a, 2 * tp + half, lane, T, P, acc);
-                    pass1_consume(acc, half);
+                    load_tile<MODE, DC>(Ab, 2 * tp + half, lane, T);
+                    screen_tile<MODE, DC>(Nb, 2 * tp + half, lane, T, P, acc);
+                    consume(acc, half);
                 }
+                store(tp);
             }
+        };
+        {
+            auto no_store = [](int) {};
+            if (a.lds_tiles)
+                screen_pass(BoolTag<true>{}, pass1_consume, no_store);
+            else
+                screen_pass(BoolTag<false>{}, pass1_consume, no_store);
         }
         // thresholds: a lane's jsel-th smallest group minimum (negative values,
         // from rounding, count as 0), as a key.  BF16 mode screens each half of
@@ -744,7 +781,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         unsigned long long nonempty[2] = {0ull, 0ull};
         {
             unsigned word[2] = {0u, 0u};
-            auto pass2_consume = [&](const f32x16 (&acc)[2]) {
+            auto pass2_consume = [&](const f32x16 (&acc)[2], int) {
 #pragma unroll
                 for (int p = 0; p < 2; ++p)
 #pragma unroll
@@ -759,17 +796,10 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                     nonempty[p] |= (unsigned long long)(wd != 0u) << tp;
                 }
             };
-            TileRegs<MODE, DC> T;
-            for (int tp = 0; tp < W; ++tp) {
-#pragma unroll
-                for (int half = 0; half < 2; ++half) {
-                    f32x16 acc[2];
-                    load_tile<MODE, DC>(a, 2 * tp + half, lane, T);
-                    screen_tile<MODE, DC>(a, 2 * tp + half, lane, T, P, acc);
-                    pass2_consume(acc);
-                }
-                pass2_store(tp);
-            }
+            if (a.lds_tiles)
+                screen_pass(BoolTag<true>{}, pass2_consume, pass2_store);
+            else
+                screen_pass(BoolTag<false>{}, pass2_consume, pass2_store);
         }
         // Certificate bound per point: a non-candidate's exact distance^2 exceeds
         // tau + |x - c|^2 - E, E a rigorous bound of the screen's error.  With

@@ -770,19 +770,24 @@ hipError_t launch_embed(const EmbedArgs &a0, int mode, int kp, int num_cus, size
     // CU: 3 waves per SIMD in BF16 mode, 2 in FP32 mode) still fits beside
     // them; otherwise rescore from global memory with 4-wave blocks, several
     // per CU.
+    // The screen operands (A tiles and norms, read by every wave twice per 64
+    // points) join them in LDS when that still fits.
     const int max_wpb = main_max_block(mode, dc, kp) / 64;
     int wpb;
     const size_t fixed = CENT_LDS_BYTES + order_lds_bytes(a.g);
+    const size_t tiles = tile_lds_bytes(mode, a.ntiles, dc);
+    a.lds_tiles = 0;
     if (fixed + rows + (size_t)max_wpb * wsm <= lds_per_block) {
         a.lds_rows = 1;
         wpb = max_wpb;
+        if (fixed + rows + tiles + (size_t)max_wpb * wsm <= lds_per_block) a.lds_tiles = 1;
     } else {
         a.lds_rows = 0;
         wpb = (int)((lds_per_block - fixed) / wsm);
         if (wpb > 4) wpb = 4;
         if (wpb < 1) wpb = 1;
     }
-    const size_t smem = fixed + (a.lds_rows ? rows : 0) + (size_t)wpb * wsm;
+    const size_t smem = fixed + (a.lds_rows ? rows : 0) + (a.lds_tiles ? tiles : 0) + (size_t)wpb * wsm;
     const int block = 64 * wpb;
     if (mode == 0) {
         if (kp == 8) return launch_main_m0_kp8(a, dc, block, smem, num_cus, s);

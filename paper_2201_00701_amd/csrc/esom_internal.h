@@ -90,6 +90,7 @@ struct EmbedArgs {
     unsigned long long *counters;
     int knn_only;  // 1: only write knn outputs (no projection)
     int lds_rows;  // 1: the block stages Lpad in LDS (row stride dp + 4 floats)
+    int lds_tiles; // 1: the block stages the screen operands (A tiles, norms) in LDS
     int x_vec4;    // 1: d == dp, X 16-byte aligned and ldx % 4 == 0 (rows load as float4)
     // Optional per-point mark beside knn outputs (serving cache): 1 when the
     // point's neighbours came from the exact path because of the screen

@@ -183,6 +183,19 @@ __device__ __forceinline__ float vmin32(float a, float b, float ninf) {
     return __builtin_amdgcn_fmed3f(a, b, ninf);
 }
 
+// x * y as a 24-bit multiply (full rate); the compiler otherwise emits a
+// 32-bit multiply, which issues at a quarter of the rate.  x, y < 2^24 and
+// x * y < 2^32.
+__device__ __forceinline__ unsigned mul24(unsigned x, unsigned y) {
+    unsigned r;
+    asm("v_mul_u32_u24 %0, %1, %2" : "=v"(r) : "v"(x), "s"(y));
+    return r;
+}
+template <int RS>
+__device__ __forceinline__ unsigned row_offset(int j) {
+    return mul24((unsigned)j, (unsigned)RS);
+}
+
 // -inf in a scalar register, opaque to the compiler.
 __device__ __forceinline__ float opaque_neg_inf() {
     float r;
@@ -454,7 +467,7 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
 #pragma unroll
         for (int qi = 0; qi < KP - 1; ++qi) {
             if (qi < a.kact - 1) {
-                const unsigned rowoff = (unsigned)iposL[jq[qi]] * (unsigned)a.g;
+                const unsigned rowoff = mul24(iposL[jq[qi]], (unsigned)a.g);
                 float2 pv[KP];
 #pragma unroll
                 for (int qj = qi + 1; qj < KP; ++qj)
@@ -893,7 +906,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 const int j = act ? 64 * ctp + 2 * (bit & 31) + (bit >> 5) : 0;
                 float acc = 0.f;
                 if (a.lds_rows) {
-                    const float4 *Lr = reinterpret_cast<const float4 *>(rowsL + (size_t)j * RS);
+                    const float4 *Lr = reinterpret_cast<const float4 *>(rowsL + row_offset<RS>(j));
 #pragma unroll
                     for (int q = 0; q < DP / 4; ++q) {
                         const float4 lv = Lr[q];

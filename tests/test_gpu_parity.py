@@ -147,6 +147,8 @@ EDGE = [
     ("d100_bf16", 400, 100, 128, 16, "bf16", {}),
     ("d100_fp32_slowpath", 300, 100, 128, 16, "fp32", {}),
     ("g2000", 500, 16, 2000, 16, "bf16", {}),
+    ("g4096_max_fast_bf16", 300, 8, 4096, 16, "bf16", {}),   # 64 tile pairs: every mask bit
+    ("g4096_max_fast_fp32", 300, 8, 4096, 16, "fp32", {}),
     ("g5000_slowpath", 200, 8, 5000, 8, "fp32", {}),
     ("adjust_half", 500, 10, 100, 10, "fp32", {"adjust": 0.5}),
     ("boost_2_gravity0", 500, 10, 100, 10, "bf16", {"boost": 2.0, "gravity": 0.0}),

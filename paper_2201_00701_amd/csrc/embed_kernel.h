@@ -566,7 +566,10 @@ __global__ void __launch_bounds__(256) embed_project(EmbedArgs a) {
     for (int e = threadIdx.x; e < a.g; e += blockDim.x) iposL[e] = (unsigned short)a.ipos[e];
     __syncthreads();
     const int64_t nwt = (a.n + 63) / 64;
-    for (int64_t wt = (int64_t)blockIdx.x * wpb + wave; wt < nwt; wt += (int64_t)gridDim.x * wpb) {
+    // Tile wt goes to block wt mod grid, wave (wt / grid) mod wpb: the last,
+    // partial round of tiles then spreads over all blocks (CUs) instead of
+    // filling the first few.
+    for (int64_t wt = (int64_t)wave * gridDim.x + blockIdx.x; wt < nwt; wt += (int64_t)gridDim.x * wpb) {
         const int64_t pi = wt * 64 + lane;
         const bool valid = pi < a.n;
         double sk[KP];
@@ -653,7 +656,10 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
 
     unsigned long long st_cand = 0;
     const int64_t nwt = (a.n + 63) / 64;
-    for (int64_t wt = (int64_t)blockIdx.x * wpb + wave; wt < nwt; wt += (int64_t)gridDim.x * wpb) {
+    // Tile wt goes to block wt mod grid, wave (wt / grid) mod wpb: the last,
+    // partial round of tiles then spreads over all blocks (CUs) instead of
+    // filling the first few.
+    for (int64_t wt = (int64_t)wave * gridDim.x + blockIdx.x; wt < nwt; wt += (int64_t)gridDim.x * wpb) {
         const int64_t pbase = wt * 64;
 
         // ---------------- point operands (centred), and |x - c|^2

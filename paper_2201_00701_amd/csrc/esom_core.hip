@@ -183,54 +183,70 @@ __global__ void __launch_bounds__(1024) prep_order(int g, const int *__restrict_
 __device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict__ L, const int *__restrict__ perm, int g,
                                int gpad, int d, int dp, int mode, const float *__restrict__ cent,
                                void *__restrict__ A, float *__restrict__ norms,
-                               float *__restrict__ Lpad, float *__restrict__ lmax) {
-    const int j = blk * (blockDim.x / 64) + (threadIdx.x >> 6);
+                               float *__restrict__ Lpad, float *__restrict__ lmax, unsigned *wmax) {
+    // wmax: 2 x (waves per block) words of LDS for the block's two maxima
+    const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
+    const int j = blk * nw + wv;
     const int lane = threadIdx.x & 63;
-    if (j >= gpad) return;
-    // Position j sits in tile pair j / 64, screen half j % 2, tile parity
-    // (j / 32) % 2 and accumulator register (j / 2) % 16, so that bit b of a
-    // candidate-bitmap word (16 parity + register) is position
-    // 64 tile_pair + 2 b + half: the two halves of a point's screen
-    // interleave, and each sees every other landmark of the order.  MFMA 32x32
-    // output row m sits in lane half (m / 4) % 2, register 4 (m / 8) + m % 4.
-    const int rr = (j / 2) % 16, hj = j % 2;
-    const int t = 2 * (j / 64) + (j / 32) % 2, m = 8 * (rr >> 2) + 4 * hj + (rr & 3);
-    const int dc = dp / 16;
-    const bool real = j < g;
-    const size_t src = real ? (size_t)perm[j] * d : 0;
-    double nrm = 0.0, qe = 0.0;  // |L_j - c|^2, |BF16 quantisation error of -2 (L_j - c)|^2
-    for (int q = lane; q < dp; q += 64) {
-        const float lv = (real && q < d) ? L[src + q] : 0.f;
-        const float c = (real && q < d) ? lv - cent[q] : 0.f;
-        nrm += (double)c * (double)c;
-        if (real) Lpad[(size_t)j * dp + q] = lv;
-        const float a2 = -2.f * c;
-        if (mode == 1) {
-            // A_bf16[t][c][lane = 32 h + m][e], dim = 16 c + 8 h + e
-            const int cc = q / 16, hh = (q % 16) / 8, e = q % 8;
-            unsigned u = __float_as_uint(a2);
-            u += 0x7FFFu + ((u >> 16) & 1u);
-            const double qd = (double)__uint_as_float(u & 0xFFFF0000u) - (double)a2;
-            qe += qd * qd;
-            reinterpret_cast<unsigned short *>(A)[(((size_t)t * dc + cc) * 64 + 32 * hh + m) * 8 + e] =
-                (unsigned short)(u >> 16);
-        } else {
-            // A_f32[t][s][lane = 32 h + m], dim = 2 s + h
-            const int s = q / 2, hh = q % 2;
-            reinterpret_cast<float *>(A)[((size_t)t * (dp / 2) + s) * 64 + 32 * hh + m] = a2;
+    if (j >= gpad) {
+        if (lane == 0) wmax[wv] = wmax[nw + wv] = 0u;
+    } else {
+        // Position j sits in tile pair j / 64, screen half j % 2, tile parity
+        // (j / 32) % 2 and accumulator register (j / 2) % 16, so that bit b of a
+        // candidate-bitmap word (16 parity + register) is position
+        // 64 tile_pair + 2 b + half: the two halves of a point's screen
+        // interleave, and each sees every other landmark of the order.  MFMA 32x32
+        // output row m sits in lane half (m / 4) % 2, register 4 (m / 8) + m % 4.
+        const int rr = (j / 2) % 16, hj = j % 2;
+        const int t = 2 * (j / 64) + (j / 32) % 2, m = 8 * (rr >> 2) + 4 * hj + (rr & 3);
+        const int dc = dp / 16;
+        const bool real = j < g;
+        const size_t src = real ? (size_t)perm[j] * d : 0;
+        double nrm = 0.0, qe = 0.0;  // |L_j - c|^2, |BF16 quantisation error of -2 (L_j - c)|^2
+        for (int q = lane; q < dp; q += 64) {
+            const float lv = (real && q < d) ? L[src + q] : 0.f;
+            const float c = (real && q < d) ? lv - cent[q] : 0.f;
+            nrm += (double)c * (double)c;
+            if (real) Lpad[(size_t)j * dp + q] = lv;
+            const float a2 = -2.f * c;
+            if (mode == 1) {
+                // A_bf16[t][c][lane = 32 h + m][e], dim = 16 c + 8 h + e
+                const int cc = q / 16, hh = (q % 16) / 8, e = q % 8;
+                unsigned u = __float_as_uint(a2);
+                u += 0x7FFFu + ((u >> 16) & 1u);
+                const double qd = (double)__uint_as_float(u & 0xFFFF0000u) - (double)a2;
+                qe += qd * qd;
+                reinterpret_cast<unsigned short *>(A)[(((size_t)t * dc + cc) * 64 + 32 * hh + m) * 8 + e] =
+                    (unsigned short)(u >> 16);
+            } else {
+                // A_f32[t][s][lane = 32 h + m], dim = 2 s + h
+                const int s = q / 2, hh = q % 2;
+                reinterpret_cast<float *>(A)[((size_t)t * (dp / 2) + s) * 64 + 32 * hh + m] = a2;
+            }
         }
-    }
 #pragma unroll
-    for (int o = 32; o > 0; o >>= 1) {
-        nrm += __shfl_xor(nrm, o);
-        qe += __shfl_xor(qe, o);
-    }
-    if (lane == 0) {
-        norms[((size_t)t * 2 + hj) * 16 + rr] = real ? (float)nrm : INFINITY;
-        if (real) {
-            atomicMax(reinterpret_cast<unsigned *>(lmax), __float_as_uint((float)sqrt(nrm) * 1.0000002f));
-            atomicMax(reinterpret_cast<unsigned *>(lmax) + 1, __float_as_uint((float)sqrt(qe) * 1.0000002f));
+        for (int o = 32; o > 0; o >>= 1) {
+            nrm += __shfl_xor(nrm, o);
+            qe += __shfl_xor(qe, o);
         }
+        if (lane == 0) {
+            norms[((size_t)t * 2 + hj) * 16 + rr] = real ? (float)nrm : INFINITY;
+            // non-negative floats: integer order is float order
+            wmax[wv] = real ? __float_as_uint((float)sqrt(nrm) * 1.0000002f) : 0u;
+            wmax[nw + wv] = real ? __float_as_uint((float)sqrt(qe) * 1.0000002f) : 0u;
+        }
+    }
+    // one atomic per block and maximum (the landmark blocks all update the
+    // same two words)
+    __syncthreads();
+    if (threadIdx.x == 0) {
+        unsigned m0 = 0u, m1 = 0u;
+        for (int w = 0; w < nw; ++w) {
+            m0 = max(m0, wmax[w]);
+            m1 = max(m1, wmax[nw + w]);
+        }
+        if (m0) atomicMax(reinterpret_cast<unsigned *>(lmax), m0);
+        if (m1) atomicMax(reinterpret_cast<unsigned *>(lmax) + 1, m1);
     }
 }
 
@@ -300,7 +316,8 @@ __global__ void __launch_bounds__(256) prep_tables(const float *__restrict__ L, 
                                                    float2 *__restrict__ pairs) {
     extern __shared__ __align__(16) float prs[];
     if ((int)blockIdx.x < nlb)
-        prep_landmarks((int)blockIdx.x, L, perm, g, gpad, d, dp, mode, cent, A, norms, Lpad, lmax);
+        prep_landmarks((int)blockIdx.x, L, perm, g, gpad, d, dp, mode, cent, A, norms, Lpad, lmax,
+                       reinterpret_cast<unsigned *>(prs));
     else
         prep_pairs((int)blockIdx.x - nlb, prs, L, l2d, perm, g, d, pairs);
 }

@@ -45,12 +45,38 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr float U32 = 5.9604645e-08f;     // 2^-24, FP32 unit roundoff
 constexpr float ILL_PAIR = 64.0f;         // max(delta^2)/(2|L_u-L_v|^2) beyond this: exact path
 constexpr double ILL_COND = 64.0;         // (tr/2)^2/det beyond this: exact path
+// Cutoff weights below this are recomputed from FP64 distances: c = 1 - exp(A
+// (delta_q - delta_k) / delta_k) takes its relative accuracy from the difference
+// delta_q - delta_k, which FP32 distances only give to ~u delta_k, so a weight
+// c ~ A u carries a relative error near 1 (and a system held only by such a
+// weight moves accordingly).  Above it the relative error is at most
+// 2 A (d_pad + 3) u / C_REFINE.  Done for k <= 8 (see embed_main).
+constexpr float C_REFINE = 1.0f / 32.0f;
+constexpr float LN_1M_CREFINE = -0.031748698f;  // ln(1 - C_REFINE)
+constexpr int N_REFINE = 4;                      // refined weights per point at most
 
 // Largest block of the fused kernel: 12 waves (3 per SIMD, 168 registers per
 // lane) where the register budget of the instantiation allows it (BF16, padded
 // dimension <= 32, k <= 16), else 8 waves (256 registers).
 __host__ __device__ constexpr int main_max_block(int mode, int dc, int kp) {
     return (mode == 1 && dc <= 2 && kp <= 16) ? 768 : 512;
+}
+
+// 1 - exp(z) for z <= 0 with full relative accuracy near 0: Taylor series
+// through z^7 for |z| < 1/8 (truncation below 2e-11 relative), else 1 - exp(z)
+// directly (then 1 - exp(z) > 0.11 and its rounding is relatively small).
+__device__ __forceinline__ float one_minus_exp(float z) {
+    if (z > -0.125f) {
+        float p = 1.f / 5040.f;
+        p = fmaf(p, z, 1.f / 720.f);
+        p = fmaf(p, z, 1.f / 120.f);
+        p = fmaf(p, z, 1.f / 24.f);
+        p = fmaf(p, z, 1.f / 6.f);
+        p = fmaf(p, z, 0.5f);
+        p = fmaf(p, z, 1.f);
+        return fmaxf(-z * p, 0.f);
+    }
+    return 1.f - __expf(z);
 }
 
 __device__ __forceinline__ unsigned bf16_bits_rne(float f) {
@@ -347,15 +373,79 @@ __device__ __forceinline__ void screen_tile(const float *Nbase, int t, int lane,
     }
 }
 
+// Cutoff weights c = 1 - exp(A (delta_q - delta_k) / delta_k) of the active
+// neighbours whose FP32 value is below C_REFINE, from FP64 distances.  sk: the
+// k nearest as sorted (delta^2, index) keys.  d2x(j) returns the FP64 squared
+// distance from the lane's point to landmark j; it is called by all lanes
+// together, with a valid landmark on every lane.  c decreases along the sorted
+// list, so the weights to refine are the lane's last nref active ones: on
+// return cref[r-1] holds the weight of neighbour kact - r for r = 1..nref
+// (nref <= N_REFINE).  Returns R_NEARTIE when the FP64 distances order a
+// refined neighbour after the k-th (the exact path then ranks the point again)
+// and R_ILLCOND when more than N_REFINE weights need it (rare: 0.03% of the
+// points of 1M x 32-D with 400 landmarks even at k = 16).
+template <int KP, class D2X>
+__device__ __forceinline__ unsigned refine_cutoffs(const EmbedArgs &a, const double (&sk)[KP], bool valid,
+                                                   D2X &&d2x, float (&cref)[N_REFINE], int &nref) {
+    nref = 0;
+#pragma unroll
+    for (int r = 0; r < N_REFINE; ++r) cref[r] = 0.f;
+    if (!a.use_cutoff) return 0u;
+    float d2k = 0.f;
+    int jk = 0;
+#pragma unroll
+    for (int q = 0; q < KP; ++q) {
+        if (q == a.k - 1) {
+            d2k = key_d2(sk[q]);
+            jk = key_idx(sk[q]);
+        }
+    }
+    // c < C_REFINE  <=>  delta_q / delta_k > 1 + ln(1 - C_REFINE) / A
+    const float f = 1.f + LN_1M_CREFINE / a.cutoff;
+    const float lim = f > 0.f ? d2k * f * f : 0.f;
+#pragma unroll
+    for (int q = 0; q < KP; ++q)
+        if (valid && q < a.kact && key_d2(sk[q]) > lim) ++nref;
+    unsigned reason = 0u;
+    if (nref > N_REFINE) {
+        reason |= R_ILLCOND;
+        nref = N_REFINE;
+    }
+    if (__ballot(nref > 0) == 0ull) return reason;
+    const double d2k64 = d2x(jk);
+    const float dk32 = __builtin_amdgcn_sqrtf((float)d2k64);
+#pragma unroll
+    for (int r = 1; r <= N_REFINE; ++r) {
+        if (__ballot(r <= nref) == 0ull) break;
+        const bool act = r <= nref;
+        int jt = jk;
+#pragma unroll
+        for (int q = 0; q < KP; ++q)
+            if (act && q == a.kact - r) jt = key_idx(sk[q]);
+        const double d2t = d2x(jt);
+        // only the difference needs FP64: it keeps its relative accuracy
+        // through the conversion, and the rest is well conditioned
+        const float dd = (float)(d2t - d2k64);
+        const float den = (__builtin_amdgcn_sqrtf((float)d2t) + dk32) * dk32;
+        const float z = den > 0.f ? a.cutoff * dd / den : 0.f;
+        if (act && (d2t > d2k64 || (d2t == d2k64 && jt > jk))) reason |= R_NEARTIE;
+        cref[r - 1] = one_minus_exp(z);
+    }
+    return reason;
+}
+
 // Phase C for one point (lane): scores from the k sorted distances, the pair
 // terms, the FP64 2x2 solve and the output store.  sk holds the k nearest as
 // packed (delta^2, index) keys, ascending.  Returns the accumulated fallback
 // reasons; the output is written only when there is none.
+// The cutoff weight of neighbour kact - r comes from cref[r-1] for r = 1..nref
+// (see refine_cutoffs).
 template <int KP>
 __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const double (&sk)[KP],
                                                   int lane, bool valid, long long pi, unsigned reason,
                                                   float *nbD2, float *nbS, unsigned short *nbI,
-                                                  const unsigned short *iposL) {
+                                                  const unsigned short *iposL, const float (&cref)[N_REFINE],
+                                                  int nref) {
     float d2q[KP], dl[KP], sq[KP], lxq[KP], lyq[KP];
     int jq[KP];
     float mu = 0.f;
@@ -381,8 +471,7 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
     }
     var /= a.Wk;
     const float dk = __builtin_amdgcn_sqrtf(d2k);
-    // cutoff argument A (delta_q - delta_k) / delta_k; 1 - exp(.) loses only
-    // absolute accuracy ~u, negligible for a weight that is then tiny
+    // cutoff argument A (delta_q - delta_k) / delta_k from the FP32 distances
     const float cut_scale = a.cutoff * __builtin_amdgcn_rcpf(dk);
     const bool degenerate = d2q[0] == d2k;
     const bool flat = !(var > 1e-30f * mu * mu);
@@ -402,7 +491,12 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
         sq[q] = 0.f;
         if (q < a.k) {
             const float e = flat ? 1.f : __expf((mu - dl[q]) * isig);
-            const float c = a.use_cutoff ? 1.f - __expf((dl[q] - dk) * cut_scale) : 1.f;
+            float c = a.use_cutoff ? 1.f - __expf((dl[q] - dk) * cut_scale) : 1.f;
+            if constexpr (KP <= 8) {
+#pragma unroll
+                for (int r = 1; r <= N_REFINE; ++r)
+                    if (r <= nref && q == a.kact - r) c = cref[r - 1];
+            }
             sq[q] = degenerate ? 0.f : e * c;
             ssum += sq[q];
             const float gs = a.gravity * sq[q];
@@ -585,7 +679,20 @@ __global__ void __launch_bounds__(256) embed_project(EmbedArgs a) {
         for (int q = 0; q < KP; ++q)
             if (q == a.k - 1) d2k = key_d2(sk[q]);
         const float thr = kth_bound(d2k, a.dp);
-        reason = project_point<KP>(a, sk, lane, valid, pi, reason, nbD2, nbS, nbI, iposL);
+        const float *xr = a.X + (valid ? pi : 0) * a.ldx;
+        auto d2x = [&](int jl) -> double {
+            const float *Lr = a.Lpad + (size_t)iposL[jl] * a.dp;
+            double acc = 0.0;
+            for (int t = 0; t < a.d; ++t) {
+                const double e = (double)xr[t] - (double)Lr[t];
+                acc = fma(e, e, acc);
+            }
+            return acc;
+        };
+        float cref[N_REFINE] = {};
+        int nref = 0;
+        if constexpr (KP <= 8) reason |= refine_cutoffs<KP>(a, sk, valid, d2x, cref, nref);
+        reason = project_point<KP>(a, sk, lane, valid, pi, reason, nbD2, nbS, nbI, iposL, cref, nref);
         if (valid && reason) {
             const unsigned long long slot = atomicAdd(&a.counters[C_FB_LEN], 1ull);
             a.fb_list[slot] = (int32_t)pi;
@@ -962,6 +1069,61 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             if (m > a.k && d2k1 - d2k <= 2.f * (DP + 3) * U32 * d2k1) reason |= R_NEARTIE;
         }
 
+        // FP64 distances for small cutoff weights (k <= 8 only), while the
+        // point's row is in registers; landmark rows from the LDS copy or the
+        // padded array (zero past d in both).  A weight's FP32 error matters when
+        // its pairs compete with gravity alone in some direction, which needs
+        // the other neighbours' pairs to be rank-deficient in 2-D: plausible
+        // for a few neighbours; with more, the strong pairs fix both directions
+        // or the system is flagged as ill-conditioned.  At k <= 16 the code
+        // alone cost 8% of this kernel (register pressure), used or not.
+        float cref[N_REFINE] = {};
+        int nref = 0;
+        if constexpr (KP <= 8) {
+            if (!a.knn_only) {
+                // rows of more than 64 dimensions are read again from memory
+                // instead of being kept in registers past the walk
+                const float *xr = a.X + (valid ? pi : 0) * a.ldx;
+                auto d2x = [&](int jl) -> double {
+                    const unsigned pos = iposL[jl];
+                    const float4 *Lr = a.lds_rows ? reinterpret_cast<const float4 *>(rowsL + row_offset<RS>(pos))
+                                                  : reinterpret_cast<const float4 *>(a.Lpad + (size_t)pos * DP);
+                    double acc = 0.0;
+                    auto add4 = [&](float4 xv, float4 lv) {
+                        const double e0 = (double)xv.x - (double)lv.x;
+                        const double e1 = (double)xv.y - (double)lv.y;
+                        const double e2 = (double)xv.z - (double)lv.z;
+                        const double e3 = (double)xv.w - (double)lv.w;
+                        acc = fma(e0, e0, acc);
+                        acc = fma(e1, e1, acc);
+                        acc = fma(e2, e2, acc);
+                        acc = fma(e3, e3, acc);
+                    };
+                    if constexpr (DC <= 4) {
+#pragma unroll
+                        for (int q = 0; q < DP / 4; ++q)
+                            add4(make_float4(x[4 * q], x[4 * q + 1], x[4 * q + 2], x[4 * q + 3]), Lr[q]);
+                    } else {
+#pragma unroll 4
+                        for (int q = 0; q < DP / 4; ++q) {
+                            float4 xv;
+                            if (a.x_vec4) {
+                                xv = reinterpret_cast<const float4 *>(xr)[q];
+                            } else {
+                                xv.x = 4 * q < a.d ? xr[min(4 * q, a.d - 1)] : 0.f;
+                                xv.y = 4 * q + 1 < a.d ? xr[min(4 * q + 1, a.d - 1)] : 0.f;
+                                xv.z = 4 * q + 2 < a.d ? xr[min(4 * q + 2, a.d - 1)] : 0.f;
+                                xv.w = 4 * q + 3 < a.d ? xr[min(4 * q + 3, a.d - 1)] : 0.f;
+                            }
+                            add4(xv, Lr[q]);
+                        }
+                    }
+                    return acc;
+                };
+                reason |= refine_cutoffs<KP>(a, sk, valid, d2x, cref, nref);
+            }
+        }
+
         // knn outputs (the exact path rewrites those of uncertified / near-tie points)
         if (valid && a.knn_mark) a.knn_mark[pi] = (reason & (R_UNCERT | R_NEARTIE)) ? 1 : 0;
         if (valid && (a.knn_idx || a.knn_d2)) {
@@ -976,7 +1138,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
 
         if (!a.knn_only) {
             __builtin_amdgcn_wave_barrier();
-            reason = project_point<KP>(a, sk, lane, valid, pi, reason, nbD2, nbS, nbI, iposL);
+            reason = project_point<KP>(a, sk, lane, valid, pi, reason, nbD2, nbS, nbI, iposL, cref, nref);
         }
         if (valid && reason) {
             const unsigned long long slot = atomicAdd(&a.counters[C_FB_LEN], 1ull);

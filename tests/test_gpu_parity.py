@@ -216,22 +216,24 @@ def test_many_tied_landmarks(torch_dev, ctx, oracle_mod):
         check_parity(X, L, l, 8, out, idx, ref, float(np.ptp(l)), "ties/" + mode)
 
 
-def _near_cutoff_problem(n=512, d=16, seed=23):
-    """Every point gets its own three landmarks at distances 1, 2 and 2 (1 + eps)
-    with eps log-uniform in [1e-8, 1e-3]; the points sit far apart, so with
-    k = 3 each point has one weighted pair whose cutoff weight is ~A eps.  The
-    grid positions are shuffled, so a pair spans a large part of the grid."""
+def _near_cutoff_problem(n=512, d=16, seed=23, m=3):
+    """Every point gets m landmarks of its own: m - 2 at distances uniform in
+    [1, 1.8], then 2 and 2 (1 + eps) with eps log-uniform in [1e-8, 1e-3].  The
+    points sit far apart, so with k = m the (k-1)-th neighbour's cutoff weight
+    is ~A eps (with m = 3 it carries the only weighted pair).  The grid
+    positions are shuffled, so a pair spans a large part of the grid."""
     rng = np.random.default_rng(seed)
     Xc = (50.0 * rng.standard_normal((n, d))).astype(np.float32)
     eps = 10.0 ** rng.uniform(-8, -3, n)
-    L = np.empty((3 * n, d), np.float64)
-    for j, r in enumerate((np.ones(n), 2.0 * np.ones(n), 2.0 * (1.0 + eps))):
+    radii = [rng.uniform(1.0, 1.8, n) for _ in range(m - 2)] + [2.0 * np.ones(n), 2.0 * (1.0 + eps)]
+    L = np.empty((m * n, d), np.float64)
+    for j, r in enumerate(radii):
         u = rng.standard_normal((n, d))
         u /= np.linalg.norm(u, axis=1, keepdims=True)
-        L[j::3] = Xc + r[:, None] * u
+        L[j::m] = Xc + r[:, None] * u
     from paper_2201_00701_amd import synth
-    l = synth.grid2d(3 * n)
-    return Xc, L.astype(np.float32), np.ascontiguousarray(l[rng.permutation(3 * n)])
+    l = synth.grid2d(m * n)
+    return Xc, L.astype(np.float32), np.ascontiguousarray(l[rng.permutation(m * n)])
 
 
 @pytest.mark.parametrize("mode", ["fp32", "bf16"])
@@ -247,6 +249,16 @@ def test_cutoff_weight_near_tie(torch_dev, ctx, oracle_mod, mode):
         out, idx, _ = run_case(torch_dev, ctx, X, L, l, 3, mode, adjust=adjust)
         ref = oracle_mod.embed(X, L, l, 3, adjust=adjust, threads=8)
         check_parity(X, L, l, 3, out, idx, ref, span, "near-cutoff/%s/a%g" % (mode, adjust))
+    # more neighbours (no FP64 refinement past k = 8): the other pairs hold both
+    # directions, so the weak weight's FP32 error stays small
+    for k in (9, 16):
+        X, L, l = _near_cutoff_problem(n=256, m=k, seed=29 + k)
+        span = float(max(np.ptp(l[:, 0]), np.ptp(l[:, 1])))
+        for adjust in (1.0, 0.0):
+            _say("case near-cutoff constructed k=%d mode=%s adjust=%g" % (k, mode, adjust))
+            out, idx, _ = run_case(torch_dev, ctx, X, L, l, k, mode, adjust=adjust)
+            ref = oracle_mod.embed(X, L, l, k, adjust=adjust, threads=8)
+            check_parity(X, L, l, k, out, idx, ref, span, "near-cutoff/k%d/%s/a%g" % (k, mode, adjust))
     # a random workload where one point's 2nd and 3rd distances differ by 2.5e-5
     # relative (found by a randomized sweep)
     X, L, l = _problem(558035534, 777, 24, 2047)

@@ -393,3 +393,64 @@ def test_threads_do_not_change_results(oracle_mod):
     b = oracle_mod.embed(X, L, l, 9, threads=4)
     np.testing.assert_array_equal(a["out"], b["out"])
     np.testing.assert_array_equal(a["idx"], b["idx"])
+
+
+# ---------------------------------------------------------------- FP32 distances and the cutoff
+
+def _project_given_scores(x, L, l, nb, s, adjust, gravity=1e-5):
+    """Normal equations of the pair objective for given scores (FP64)."""
+    M = np.zeros((2, 2))
+    r = np.zeros(2)
+    x = x.astype(np.float64)
+    for i in range(len(nb)):
+        for j in range(i + 1, len(nb)):
+            Lu, Lv = L[nb[i]].astype(np.float64), L[nb[j]].astype(np.float64)
+            H = Lv - Lu
+            D = (x - Lu) @ H / (H @ H)
+            lu = l[nb[i]].astype(np.float64)
+            h = l[nb[j]].astype(np.float64) - lu
+            hh = h @ h
+            q = s[i] * s[j] * hh ** -adjust
+            M += q * np.outer(h, h) / hh
+            r += q * h * (D + h @ lu / hh)
+    for i in range(len(nb)):
+        M += gravity * s[i] * np.eye(2)
+        r += gravity * s[i] * l[nb[i]]
+    return np.linalg.solve(M, r)
+
+
+def _fp32_d2(x, row):
+    acc = np.float32(0)
+    for a, b in zip(x, row):
+        e = np.float32(a - b)
+        acc = np.float32(acc + np.float32(e * e))
+    return float(acc)
+
+
+@pytest.mark.parametrize("k,rows,expect_over", [(3, range(0, 512, 2), True), (16, range(0, 256, 8), False)])
+def test_cutoff_weight_sensitivity_to_fp32_distances(oracle_mod, k, rows, expect_over):
+    """Scores from FP32-rounded distances, everything else in FP64.  With one
+    weighted pair (k = 3, adjust = 0) and the (k-1)-th distance within 1e-8 to
+    1e-3 of the k-th, some outputs move past 1e-4 of the grid span (the GPU
+    path recomputes such weights from FP64 distances); with k = 16 the other
+    pairs hold both directions and the same rounding stays far below it."""
+    import sys
+    sys.path.insert(0, HERE)
+    from test_gpu_parity import _near_cutoff_problem
+    oracle = oracle_mod
+    X, L, l = _near_cutoff_problem() if k == 3 else _near_cutoff_problem(n=256, m=k, seed=29 + k)
+    span = float(max(np.ptp(l[:, 0]), np.ptp(l[:, 1])))
+    ref = oracle.embed(X, L, l, k, adjust=0.0, threads=4)
+    errs = []
+    for p in rows:
+        nb = ref["idx"][p][:k]
+        s64, _ = oracle.scores(np.sqrt(ref["d2"][p][:k]), len(L))
+        d2f = np.array([_fp32_d2(X[p], L[j]) for j in nb])
+        s32, _ = oracle.scores(np.sqrt(d2f), len(L))
+        errs.append(np.abs(_project_given_scores(X[p], L, l, nb, s32, 0.0)
+                           - _project_given_scores(X[p], L, l, nb, s64, 0.0)).max())
+    worst = max(errs) / (1e-4 * span)
+    if expect_over:
+        assert worst > 1.0
+    else:
+        assert worst < 0.01

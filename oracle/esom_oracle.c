@@ -35,8 +35,11 @@
  *     non-singular (k = 3 leaves a rank-one system otherwise).
  *   - pairs whose HD or 2-D landmarks coincide exactly are skipped.
  *   - degenerate neighbourhoods (all delta equal, sum of scores zero, or a
- *     non-positive determinant) map to the centroid of the neighbours' 2-D
- *     positions.
+ *     numerically singular system, det <= 1e-9 (tr/2)^2) map to the centroid
+ *     of the neighbours' 2-D positions.  A rank-deficient system (k = 3
+ *     without gravity, or collinear 2-D neighbours) has det = 0 exactly, but
+ *     its computed det is rounding noise of either sign; the relative bound
+ *     makes the decision independent of the summation order.
  *   - ties between equal distances break by landmark index.
  *
  * Landmark update (Section "User supervision and model interaction"): one
@@ -202,7 +205,8 @@ static int project_point(const float *x, const float *L, const float *l, int g,
         }
     }
     double det = M00 * M11 - M01 * M01;
-    if (degenerate || ssum == 0.0 || !(det > 0.0)) {
+    double htr = 0.5 * (M00 + M11);
+    if (degenerate || ssum == 0.0 || !(det > 1e-9 * htr * htr)) {
         double cx = 0.0, cy = 0.0;
         for (int i = 0; i < k; ++i) {
             cx += l[2 * nb[i]];

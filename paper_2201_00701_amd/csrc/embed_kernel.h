@@ -45,6 +45,7 @@ typedef unsigned int u32x4 __attribute__((ext_vector_type(4)));
 constexpr float U32 = 5.9604645e-08f;     // 2^-24, FP32 unit roundoff
 constexpr float ILL_PAIR = 64.0f;         // max(delta^2)/(2|L_u-L_v|^2) beyond this: exact path
 constexpr double ILL_COND = 64.0;         // (tr/2)^2/det beyond this: exact path
+constexpr double SINGULAR_REL = 1e-9;     // det <= this (tr/2)^2: singular, centroid
 // Cutoff weights below this are recomputed from FP64 distances: c = 1 - exp(A
 // (delta_q - delta_k) / delta_k) takes its relative accuracy from the difference
 // delta_q - delta_k, which FP32 distances only give to ~u delta_k, so a weight

@@ -702,8 +702,11 @@ __global__ void __launch_bounds__(EX_THREADS) embed_exact(EmbedArgs a, int all_p
             for (int w = 0; w < EX_THREADS / 64; ++w)
                 for (int i = 0; i < 6; ++i) t[i] += red[6 * w + i];
             const double det = t[0] * t[2] - t[1] * t[1];
+            const double htr = 0.5 * (t[0] + t[2]);
             double px, py;
-            if (degenerate || !(t[5] > 0.0) || !(det > 0.0)) {
+            // numerically singular (a rank-deficient system, e.g. one pair and
+            // no gravity, has det = 0 up to rounding of either sign): centroid
+            if (degenerate || !(t[5] > 0.0) || !(det > SINGULAR_REL * htr * htr)) {
                 double cx = 0.0, cy = 0.0;
                 for (int q = 0; q < k; ++q) {
                     cx += nl2[2 * q];

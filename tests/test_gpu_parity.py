@@ -153,6 +153,9 @@ EDGE = [
     ("adjust_half", 500, 10, 100, 10, "fp32", {"adjust": 0.5}),
     ("boost_2_gravity0", 500, 10, 100, 10, "bf16", {"boost": 2.0, "gravity": 0.0}),
     ("candidates_k1", 500, 10, 100, 10, "bf16", {"candidates": 11}),
+    # one pair and no gravity: a rank-one system, the centroid on both sides
+    ("k3_gravity0", 500, 16, 200, 3, "bf16", {"gravity": 0.0}),
+    ("k3_gravity0_slowpath", 64, 63, 4097, 3, "fp32", {"gravity": 0.0}),
 ]
 
 

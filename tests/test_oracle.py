@@ -310,6 +310,27 @@ def test_all_equidistant_maps_to_centroid(oracle_mod):
     assert r["n_degenerate"] == 1
 
 
+def test_rank_deficient_system_maps_to_centroid(oracle_mod):
+    """k = 3 leaves one weighted pair: without gravity the 2x2 system has rank
+    one and det = 0 up to rounding (of either sign), so every point maps to the
+    centroid of its neighbours' 2-D positions.  Collinear 2-D neighbours do the
+    same at larger k.  With gravity the same points are solved."""
+    rng = np.random.default_rng(5)
+    X, L, l = _random_problem(rng, n=60, d=5, g=30)
+    r = oracle_mod.embed(X, L, l, 3, gravity=0.0)
+    cent = l[r["idx"][:, :3]].astype(np.float64).mean(1)
+    np.testing.assert_allclose(r["out"], cent, rtol=0, atol=1e-12)
+    assert r["n_degenerate"] == len(X)
+    r1 = oracle_mod.embed(X, L, l, 3)
+    assert r1["n_degenerate"] == 0
+    assert np.all(np.abs(r1["out"] - cent).max(1) > 1e-3)
+    # all landmarks on one line in 2-D: every pair direction is the same
+    l_line = np.stack([np.arange(30, dtype=np.float32), np.zeros(30, np.float32)], 1)
+    r2 = oracle_mod.embed(X, L, l_line, 6, gravity=0.0)
+    np.testing.assert_allclose(r2["out"], l_line[r2["idx"][:, :6]].astype(np.float64).mean(1),
+                               rtol=0, atol=1e-12)
+
+
 def test_invalid_arguments(oracle_mod):
     X = np.zeros((2, 3), np.float32)
     L = np.zeros((5, 3), np.float32)

@@ -272,6 +272,61 @@ def test_cutoff_weight_near_tie(torch_dev, ctx, oracle_mod, mode):
     check_parity(X, L, l, 3, out, idx, ref, span, "near-cutoff-mix/" + mode)
 
 
+def _sweep_cases(seed=11, ncase=30):
+    """Seeded random shapes and parameters: d, k, g, n, adjust, boost, gravity,
+    duplicated landmarks, points on landmarks, data and grid scales, collinear
+    2-D landmarks, k = g - 1."""
+    rng = np.random.default_rng(seed)
+    out = []
+    for c in range(ncase):
+        mode = ["fp32", "bf16"][c % 2]
+        d = int(rng.choice([1, 2, 3, 5, 8, 13, 16, 17, 24, 31, 32, 33, 40, 48, 63, 64, 65, 96, 127, 129]))
+        k = int(rng.choice([3, 4, 5, 8, 9, 12, 15, 16, 17, 20, 24, 31, 32, 33, 40]))
+        g = max(k, int(rng.choice([k, k + 1, 17, 50, 64, 65, 100, 127, 128, 129, 300, 400, 513,
+                                   1024, 2047, 2049, 4096, 4097])))
+        n = int(rng.choice([1, 2, 63, 64, 65, 127, 200, 777]))
+        extra = {}
+        if rng.random() < 0.3:
+            extra["adjust"] = float(rng.choice([0.0, 0.5, 2.0]))
+        if rng.random() < 0.2:
+            extra["boost"] = float(rng.choice([0.5, 3.0]))
+        if rng.random() < 0.2:
+            extra["gravity"] = float(rng.choice([0.0, 1e-3]))
+        out.append(dict(c=c, mode=mode, d=d, k=k, g=g, n=n, extra=extra, seed=int(rng.integers(1 << 30)),
+                        dup=rng.random() < 0.15, onl=rng.random() < 0.15,
+                        xscale=float(10.0 ** rng.uniform(-3, 3)) if rng.random() < 0.25 else None,
+                        lscale=float(10.0 ** rng.uniform(-2, 2)) if rng.random() < 0.2 else None,
+                        line=rng.random() < 0.1, kg1=rng.random() < 0.1))
+    return out
+
+
+@pytest.mark.parametrize("case", _sweep_cases(), ids=lambda cs: "sweep%d" % cs["c"])
+def test_randomized_sweep(torch_dev, ctx, oracle_mod, case):
+    cs = case
+    X, L, l = _problem(cs["seed"], cs["n"], cs["d"], cs["g"])
+    k = cs["k"]
+    if cs["dup"]:
+        L[1] = L[0]
+        l[2] = l[3]
+    if cs["onl"] and cs["n"] > 3:
+        X[:3] = L[:3]
+    if cs["xscale"] is not None:
+        X = (X * np.float32(cs["xscale"])).astype(np.float32)
+        L = (L * np.float32(cs["xscale"])).astype(np.float32)
+    if cs["lscale"] is not None:
+        l = (l * np.float32(cs["lscale"])).astype(np.float32)
+    if cs["line"]:
+        l = np.ascontiguousarray(np.stack([l[:, 0], np.zeros_like(l[:, 0])], 1))
+    if cs["kg1"] and cs["g"] - 1 <= 40 and cs["g"] > k + 1:
+        k = cs["g"] - 1
+    label = "sweep %d: %s n=%d d=%d g=%d k=%d %s" % (cs["c"], cs["mode"], cs["n"], cs["d"], cs["g"], k, cs["extra"])
+    _say("case " + label)
+    out, idx, _ = run_case(torch_dev, ctx, X, L, l, k, cs["mode"], **cs["extra"])
+    ref = oracle_mod.embed(X, L, l, k, threads=8, **cs["extra"])
+    span = float(max(np.ptp(l[:, 0]), np.ptp(l[:, 1])))
+    check_parity(X, L, l, k, out, idx, ref, span, label)
+
+
 def test_empty_input_is_noop(torch_dev, ctx):
     from paper_2201_00701_amd import esom
     L = torch_dev.zeros((10, 4), device="cuda")

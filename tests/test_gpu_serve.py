@@ -76,14 +76,16 @@ def test_alone_equals_mix_equals_direct(torch_dev, oracle_mod):
     srv.close()
 
 
-def test_resident_dataset_2d_edits_use_cache_and_graph(torch_dev):
+@pytest.mark.parametrize("k", [16, 8])
+def test_resident_dataset_2d_edits_use_cache_and_graph(torch_dev, k):
+    # k = 8 also takes the FP64 cutoff-weight refinement, on both paths
     from paper_2201_00701_amd.esom import Server
     rng = np.random.default_rng(7)
     X, L, l0 = _req(201, 40000, 32, 400, 20)
     srv = Server(0, 0, 2)
     did = srv.put(X)
     out = np.empty((len(X), 2), np.float32)
-    _say("case serve resident dataset frames")
+    _say("case serve resident dataset frames k=%d" % k)
     hits, replays = 0, 0
     l = l0.copy()
     for frame in range(8):
@@ -91,11 +93,11 @@ def test_resident_dataset_2d_edits_use_cache_and_graph(torch_dev):
             moved = rng.choice(len(l), rng.integers(1, 6), replace=False)
             l = l.copy()
             l[moved] += rng.normal(0, 0.5, (len(moved), 2)).astype(np.float32)
-        rid = srv.submit(L, l, k=16, mode="bf16", dataset=did, out=out)
+        rid = srv.submit(L, l, k=k, mode="bf16", dataset=did, out=out)
         info = srv.wait(rid, 60000)
         hits += info["cache_hit"]
         replays += info["graph_replay"]
-        ref = _direct(torch_dev, X, L, l, 16, "bf16")
+        ref = _direct(torch_dev, X, L, l, k, "bf16")
         np.testing.assert_array_equal(out, ref)
         _say("  frame %d cache_hit=%d graph_replay=%d" % (frame, info["cache_hit"],
                                                            info["graph_replay"]))
@@ -103,10 +105,10 @@ def test_resident_dataset_2d_edits_use_cache_and_graph(torch_dev):
     # a high-dimensional change invalidates the cache
     L2 = L.copy()
     L2[0] += 0.25
-    rid = srv.submit(L2, l, k=16, mode="bf16", dataset=did, out=out)
+    rid = srv.submit(L2, l, k=k, mode="bf16", dataset=did, out=out)
     info = srv.wait(rid, 60000)
     assert info["cache_hit"] == 0
-    np.testing.assert_array_equal(out, _direct(torch_dev, X, L2, l, 16, "bf16"))
+    np.testing.assert_array_equal(out, _direct(torch_dev, X, L2, l, k, "bf16"))
     srv.drop(did)
     srv.close()
 

@@ -116,15 +116,22 @@ int oracle_scores(const double *delta, int k, int g, double boost, double cutoff
             s[i] = 0.0;
         return 1;
     }
-    double W = 0.0, mu = 0.0, m2 = 0.0;
+    /* rank weights 1/i; the weighted mean, then the weighted mean of the
+     * squared deviations from it (the variance as defined, which keeps its
+     * relative accuracy however small the spread of the distances) */
+    double W = 0.0, mu = 0.0;
     for (int i = 0; i < k; ++i) {
         double w = 1.0 / (double)(i + 1);
         W += w;
         mu += w * delta[i];
-        m2 += w * delta[i] * delta[i];
     }
     mu /= W;
-    double var = m2 / W - mu * mu;
+    double var = 0.0;
+    for (int i = 0; i < k; ++i) {
+        double dev = delta[i] - mu;
+        var += dev * dev / (double)(i + 1);
+    }
+    var /= W;
     for (int i = 0; i < k; ++i) {
         double e;
         if (var <= 1e-30 * mu * mu)

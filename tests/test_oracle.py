@@ -106,6 +106,31 @@ def test_scores_all_equal_is_degenerate(oracle_mod):
     assert deg and np.all(s == 0)
 
 
+def _golden_e():
+    # e-factors of the hand-computed case delta = (1, 2, 3) (tests/golden/tscore.txt)
+    return np.array([2.281785, 0.624125, 0.170714])
+
+
+@pytest.mark.parametrize("t,flat", [(1e-9, False), (2.0 ** -52, True), (2.0 ** -51, True)])
+def test_scores_flat_spread(oracle_mod, t, flat):
+    # delta = 1 + t (0, 1, 2) is a positive affine image of the golden (1, 2, 3):
+    # the standardised exponent (mu - delta_i) / sigma is invariant under such
+    # maps, so the e-factors equal the golden ones while the variance is
+    # resolvable (t = 1e-9: sigma^2 ~ 6e-19 mu^2).  Below the flat-variance
+    # threshold (sigma^2 <= 1e-30 mu^2, spreads of a few units in the last place
+    # of double) every e-factor is 1: the scores are the cutoff factors alone.
+    delta = np.array([1.0, 1.0 + t, 1.0 + 2.0 * t])
+    s, deg = oracle_mod.scores(delta, g=10, boost=1.0, cutoff=10.0)
+    assert not deg
+    c = 1.0 - np.exp(10.0 * (delta / delta[2] - 1.0))
+    assert c[0] > 0 and c[1] > 0 and s[2] == 0.0
+    e = s[:2] / c[:2]
+    if flat:
+        np.testing.assert_allclose(e, [1.0, 1.0], rtol=1e-12)
+    else:
+        np.testing.assert_allclose(e, _golden_e()[:2], rtol=2e-5)
+
+
 # ---------------------------------------------------------------- projection
 
 
@@ -383,6 +408,26 @@ def test_som_small_sigma_equals_kmeans(oracle_mod):
     a, _ = oracle_mod.landmark_update(X, L, l, "kmeans", alpha=0.3)
     b, _ = oracle_mod.landmark_update(X, L, l, "som", alpha=0.3, sigma=1e-3)
     np.testing.assert_allclose(a, b, rtol=1e-12, atol=1e-12)
+
+
+def test_som_sigma_zero_is_lloyd_step(oracle_mod):
+    # sigma = 0: each landmark's neighbourhood is itself alone, so the SOM step
+    # is the alpha-blended Lloyd step; a landmark that owns no point stays put
+    from scipy.cluster.vq import vq
+    X, L, l = _blob_data(6)
+    L = np.concatenate([L, np.full((1, L.shape[1]), 1e4, np.float32)])
+    l = np.concatenate([l, [[5, 5]]]).astype(np.float32)
+    alpha = 0.3
+    Lnew, counts = oracle_mod.landmark_update(X, L, l, "som", alpha=alpha, sigma=0.0)
+    codes, _ = vq(X.astype(np.float64), L.astype(np.float64))
+    assert np.array_equal(np.bincount(codes, minlength=len(L)), counts)
+    assert counts[-1] == 0
+    L64 = L.astype(np.float64)
+    expect = L64.copy()
+    for j in range(len(L) - 1):
+        mean = X[codes == j].astype(np.float64).mean(0)
+        expect[j] = L64[j] + alpha * (mean - L64[j])
+    np.testing.assert_allclose(Lnew, expect, rtol=1e-12, atol=1e-12)
 
 
 def test_som_is_neighbourhood_weighted_mean(oracle_mod):

@@ -123,7 +123,9 @@ const char *esom_last_error(void);
  *   L_2d     device, g x 2 floats, row-major, contiguous
  *   out      device, n x 2 floats (written)
  *   knn_idx  device, n x k int32 or NULL: the k nearest landmark indices, sorted
- *            by (distance, index)
+ *            by (exact distance, index): entries closer than FP32 rescoring can
+ *            order are ranked again in FP64; -1 for a point without k finite
+ *            distances (non-finite input), whose output is then NaN
  *   knn_dist2 device, n x k floats or NULL: their squared distances (FP32)
  * n == 0 is a no-op.  Errors: ESOM_EINVAL for k < 3, k > g, k > ESOM_MAX_K,
  * d < 1 or > ESOM_MAX_D, g > ESOM_MAX_G, n < 0, ldx < d, NULL or misaligned

@@ -667,14 +667,25 @@ __global__ void __launch_bounds__(256) embed_project(EmbedArgs a) {
     for (int64_t wt = (int64_t)wave * gridDim.x + blockIdx.x; wt < nwt; wt += (int64_t)gridDim.x * wpb) {
         const int64_t pi = wt * 64 + lane;
         const bool valid = pi < a.n;
+        // A cached index outside [0, g) (the exact path writes -1 for a point
+        // without k finite distances) is never used for a load: it becomes
+        // landmark 0 and the point goes to the exact path, which ranks it again.
         double sk[KP];
+        bool bad_idx = false;
 #pragma unroll
         for (int q = 0; q < KP; ++q) {
             sk[q] = INFINITY;
-            if (valid && q < a.k)
-                sk[q] = pack_key(a.knn_d2[pi * a.k + q], a.knn_idx[pi * a.k + q]);
+            if (valid && q < a.k) {
+                int j = a.knn_idx[pi * a.k + q];
+                if (j < 0 || j >= a.g) {
+                    bad_idx = true;
+                    j = 0;
+                }
+                sk[q] = pack_key(a.knn_d2[pi * a.k + q], j);
+            }
         }
         unsigned reason = (valid && a.knn_mark && a.knn_mark[pi]) ? (unsigned)R_NEARTIE : 0u;
+        if (bad_idx) reason |= R_UNCERT;
         float d2k = INFINITY;
 #pragma unroll
         for (int q = 0; q < KP; ++q)
@@ -1068,6 +1079,19 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             // two rescored values are ordered correctly when their gap exceeds the sum
             // of their rounding bounds, (d_pad + 3) u each
             if (m > a.k && d2k1 - d2k <= 2.f * (DP + 3) * U32 * d2k1) reason |= R_NEARTIE;
+            // When the neighbour list itself is an output (its first entry is the
+            // nearest landmark of the landmark update), adjacent entries closer
+            // than the rounding bound go to the exact path too, so the list is
+            // ordered by exact distance.
+            if (a.knn_idx) {
+                float prev = key_d2(sk[0]);
+#pragma unroll
+                for (int q = 1; q < KP; ++q) {
+                    const float cur = key_d2(sk[q]);
+                    if (q < a.k && q < m && cur - prev <= 2.f * (DP + 3) * U32 * cur) reason |= R_NEARTIE;
+                    prev = cur;
+                }
+            }
         }
 
         // FP64 distances for small cutoff weights (k <= 8 only), while the

@@ -24,7 +24,7 @@ struct esom_ctx {
     void *arena = nullptr;
     size_t arena_bytes = 0;
     int64_t cap_n = 0;
-    int cap_g = 0, cap_dp = 0;
+    int cap_g = 0, cap_dp = 0, cap_pg = 0;
     Scratch sc;
     // landmark-update workspace
     void *uws = nullptr;
@@ -78,8 +78,9 @@ void dev_free(esom_ctx *c, void *&p, size_t bytes) {
     }
 }
 
-// Lays the embed scratch out for (n, g, dp) capacities.
-size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp) {
+// Lays the embed scratch out for (n, g, dp) capacities; the pair table holds
+// pg x pg entries (0 when no call so far needed it).
+size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg) {
     const int ntiles = ((g + TILE_PAIR - 1) / TILE_PAIR) * 2;
     char *p = static_cast<char *>(base);
     size_t off = 0;
@@ -92,7 +93,7 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp) {
     sc.prep.A = take(sizeof(float) * (size_t)ntiles * TILE * dp);
     sc.prep.norms = static_cast<float *>(take(sizeof(float) * (size_t)ntiles * TILE));
     sc.prep.Lpad = static_cast<float *>(take(sizeof(float) * (size_t)g * dp));
-    sc.prep.pairs = static_cast<float2 *>(take(sizeof(float2) * (size_t)g * g));
+    sc.prep.pairs = pg > 0 ? static_cast<float2 *>(take(sizeof(float2) * (size_t)pg * pg)) : nullptr;
     sc.prep.lmax = static_cast<float *>(take(2 * sizeof(float)));
     sc.prep.perm = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
     sc.prep.ipos = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
@@ -105,12 +106,13 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp) {
     return off;
 }
 
-int ensure_scratch(esom_ctx *c, int64_t n, int g, int dp, hipStream_t s) {
-    if (c->arena && n <= c->cap_n && g <= c->cap_g && dp <= c->cap_dp) return ESOM_OK;
+int ensure_scratch(esom_ctx *c, int64_t n, int g, int dp, int pg, hipStream_t s) {
+    if (c->arena && n <= c->cap_n && g <= c->cap_g && dp <= c->cap_dp && pg <= c->cap_pg) return ESOM_OK;
     int64_t nn = n > c->cap_n ? n + n / 4 : c->cap_n;
     int gg = g > c->cap_g ? g : c->cap_g;
     int dd = dp > c->cap_dp ? dp : c->cap_dp;
-    const size_t bytes = carve(c->sc, nullptr, nn, gg, dd);
+    int pp = pg > c->cap_pg ? pg : c->cap_pg;
+    const size_t bytes = carve(c->sc, nullptr, nn, gg, dd, pp);
     if (c->arena) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -121,14 +123,15 @@ int ensure_scratch(esom_ctx *c, int64_t n, int g, int dp, hipStream_t s) {
     }
     int st = dev_alloc(c, &c->arena, bytes);
     if (st != ESOM_OK) {
-        c->cap_n = c->cap_g = c->cap_dp = 0;
+        c->cap_n = c->cap_g = c->cap_dp = c->cap_pg = 0;
         return st;
     }
     c->arena_bytes = bytes;
-    carve(c->sc, c->arena, nn, gg, dd);
+    carve(c->sc, c->arena, nn, gg, dd, pp);
     c->cap_n = nn;
     c->cap_g = gg;
     c->cap_dp = dd;
+    c->cap_pg = pp;
     return ESOM_OK;
 }
 
@@ -181,7 +184,9 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
               float *knn_d2, int what, hipStream_t s, uint8_t *knn_mark) {
     const int knn_only = what == EMBED_KNN_ONLY;
     const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
-    int st = ensure_scratch(c, n, g, pl.dp, s);
+    // the pair table is read only by the fast kernels' projection
+    const bool need_pairs = !knn_only && pl.kp != 0 && (what == EMBED_PROJECT || pl.fast);
+    int st = ensure_scratch(c, n, g, pl.dp, need_pairs ? g : 0, s);
     if (st != ESOM_OK) return st;
     Prep &pr = c->sc.prep;
     pr.g = g;
@@ -191,6 +196,7 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
     pr.ntiles = ((g + TILE_PAIR - 1) / TILE_PAIR) * 2;
     pr.npairs = pr.ntiles / 2;
     pr.mode = P.mode;
+    pr.need_pairs = need_pairs ? 1 : 0;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     const bool timed = c->timing && !knn_only;
     if (timed) {
@@ -272,15 +278,33 @@ size_t ctx_held_bytes(const esom_ctx *c) { return c->held; }
 void ctx_trim(esom_ctx *c) {
     dev_free(c, c->arena, c->arena_bytes);
     c->arena_bytes = 0;
-    c->cap_n = c->cap_g = c->cap_dp = 0;
+    c->cap_n = c->cap_g = c->cap_dp = c->cap_pg = 0;
 }
 
 size_t embed_scratch_bytes(int64_t n, int g, int d) {
     Scratch sc;
-    return carve(sc, nullptr, n, g, 16 * ((d + 15) / 16));
+    return carve(sc, nullptr, n, g, 16 * ((d + 15) / 16), g);
 }
 
 int fail_msg(int code, const char *msg) { return fail(code, "%s", msg); }
+
+int validate_params(const esom_params &P, int g) {
+    if (g < 3 || g > ESOM_MAX_G) return fail(ESOM_EINVAL, "g = %d outside [3, %d]", g, ESOM_MAX_G);
+    if (P.k < 3 || P.k > g || P.k > ESOM_MAX_K)
+        return fail(ESOM_EINVAL, "k = %d outside [3, min(g = %d, %d)]", P.k, g, ESOM_MAX_K);
+    if (!(P.boost > 0.f) || !(P.boost * sqrt(harmonic(P.k)) < 80.0))
+        return fail(ESOM_EINVAL, "boost = %g must be > 0 with boost*sqrt(H_k) < 80", (double)P.boost);
+    if (!(P.cutoff > 0.f) || !isfinite(P.cutoff))
+        return fail(ESOM_EINVAL, "cutoff = %g must be finite and > 0", (double)P.cutoff);
+    if (!(P.gravity >= 0.f) || !isfinite(P.gravity))
+        return fail(ESOM_EINVAL, "gravity = %g must be finite and >= 0", (double)P.gravity);
+    if (!isfinite(P.adjust)) return fail(ESOM_EINVAL, "adjust must be finite");
+    if (P.mode != ESOM_MODE_FP32 && P.mode != ESOM_MODE_BF16_RESCORE)
+        return fail(ESOM_EINVAL, "unknown mode %d", P.mode);
+    if (P.candidates < 0 || P.candidates > g)
+        return fail(ESOM_EINVAL, "candidates = %d outside [0, g]", P.candidates);
+    return ESOM_OK;
+}
 
 }  // namespace esom
 
@@ -366,20 +390,8 @@ int esom_embed(esom_ctx *c, const float *X, int64_t n, int32_t d, int64_t ldx, c
     int st = validate_common(X, n, d, ldx, L_hd, g);
     if (st != ESOM_OK) return st;
     const esom_params &P = *params;
-    if (g < 3) return fail(ESOM_EINVAL, "g = %d < 3", g);
-    if (P.k < 3 || P.k > g || P.k > ESOM_MAX_K)
-        return fail(ESOM_EINVAL, "k = %d outside [3, min(g = %d, %d)]", P.k, g, ESOM_MAX_K);
-    if (!(P.boost > 0.f) || !(P.boost * sqrt(harmonic(P.k)) < 80.0))
-        return fail(ESOM_EINVAL, "boost = %g must be > 0 with boost*sqrt(H_k) < 80", (double)P.boost);
-    if (!(P.cutoff > 0.f) || !isfinite(P.cutoff))
-        return fail(ESOM_EINVAL, "cutoff = %g must be finite and > 0", (double)P.cutoff);
-    if (!(P.gravity >= 0.f) || !isfinite(P.gravity))
-        return fail(ESOM_EINVAL, "gravity = %g must be finite and >= 0", (double)P.gravity);
-    if (!isfinite(P.adjust)) return fail(ESOM_EINVAL, "adjust must be finite");
-    if (P.mode != ESOM_MODE_FP32 && P.mode != ESOM_MODE_BF16_RESCORE)
-        return fail(ESOM_EINVAL, "unknown mode %d", P.mode);
-    if (P.candidates < 0 || P.candidates > g)
-        return fail(ESOM_EINVAL, "candidates = %d outside [0, g]", P.candidates);
+    st = validate_params(P, g);
+    if (st != ESOM_OK) return st;
     if (!L_2d || !aligned4(L_2d)) return fail(ESOM_EINVAL, "L_2d is NULL or not 4-byte aligned");
     if (n > 0 && (!out || ((uintptr_t)out & 7u)))
         return fail(ESOM_EINVAL, "out is NULL or not 8-byte aligned");

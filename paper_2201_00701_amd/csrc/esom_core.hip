@@ -333,7 +333,7 @@ hipError_t launch_prep(const Prep &P, const float *L, const float *l2d, int mode
                        P.ipos);
     const int gpad = P.ntiles * TILE;
     const int nlb = (gpad + 3) / 4;
-    const int ntu = (P.g + PAIR_TILE - 1) / PAIR_TILE;
+    const int ntu = P.need_pairs ? (P.g + PAIR_TILE - 1) / PAIR_TILE : 0;
     hipLaunchKernelGGL(prep_tables, dim3((unsigned)(nlb + ntu * ntu)), dim3(256),
                        sizeof(float) * 2 * PAIR_TILE * (P.d + 1) + sizeof(float2) * 2 * PAIR_TILE, s, L, P.perm, P.g, gpad, P.d, P.dp, mode,
                        nlb, P.cent, P.A, P.norms, P.Lpad, P.lmax, l2d, P.pairs);

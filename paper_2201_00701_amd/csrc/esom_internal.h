@@ -39,11 +39,12 @@ enum Reason { R_UNCERT = 1, R_NEARTIE = 2, R_ILLCOND = 4, R_DEGEN = 8 };
 struct Prep {
     int g = 0, d = 0, dp = 0, dc = 0, ntiles = 0, npairs = 0;
     int mode = 0;
+    int need_pairs = 1;      // 0: the pair table is neither allocated nor filled
     float *cent = nullptr;   // dp      centroid of L (FP32 of an FP64 mean)
     void *A = nullptr;       // MFMA landmark operand, -2 (L - c), tile layout
     float *norms = nullptr;  // ntiles * 32: |L_j - c|^2 in MFMA row order
     float *Lpad = nullptr;   // g * dp:  L rows padded with zeros to dp
-    float2 *pairs = nullptr;  // g * g: (1 / (2 |L_u - L_v|^2), 1 / |l_v - l_u|^2), (0, 0) if skipped
+    float2 *pairs = nullptr;  // g * g (when need_pairs): (1 / (2 |L_u - L_v|^2), 1 / |l_v - l_u|^2), (0, 0) if skipped
     float *lmax = nullptr;   // 2:       max_j |L_j - c|, max_j |BF16(-2 (L_j - c)) + 2 (L_j - c)|
     // Landmark order of the screen tiles, rows and pair table: position ->
     // landmark (perm) and landmark -> position (ipos).  Landmarks that are
@@ -131,5 +132,7 @@ size_t ctx_held_bytes(const esom_ctx *c);
 void ctx_trim(esom_ctx *c);
 size_t embed_scratch_bytes(int64_t n, int g, int d);
 int fail_msg(int code, const char *msg);
+// Checks the parameters of an embed over g landmarks (the esom_embed rules).
+int validate_params(const esom_params &P, int g);
 
 }  // namespace esom

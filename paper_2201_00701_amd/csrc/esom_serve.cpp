@@ -516,25 +516,37 @@ int esom_serve_dataset_put(esom_server *S, const float *X_host, int64_t n, int32
                            uint64_t *dataset_id) {
     if (!S || !X_host || !dataset_id) return fail_msg(ESOM_EINVAL, "NULL argument");
     if (n < 1 || d < 1 || d > ESOM_MAX_D) return fail_msg(ESOM_EINVAL, "bad dataset shape");
+    if (n > (int64_t)INT32_MAX) return fail_msg(ESOM_EINVAL, "n exceeds 2^31 - 1");
     const size_t bytes = (size_t)n * d * sizeof(float);
+    // The bytes are reserved under the lock; the allocation and the upload run
+    // without it, so admissions and completions of the running slots are not
+    // held up by a large upload.
     std::unique_lock<std::mutex> lk(S->mu);
     if (S->budget && S->resident + slot_held(S) + bytes > S->budget)
         return fail_msg(ESOM_ENOMEM, "dataset does not fit the serving budget");
+    S->resident += bytes;
+    const uint64_t id = S->next_id++;
+    lk.unlock();
+    auto unreserve = [&](int code, const char *msg) {
+        std::lock_guard<std::mutex> g(S->mu);
+        S->resident -= bytes;
+        return fail_msg(code, msg);
+    };
     (void)hipSetDevice(S->device);
     auto ds = std::make_unique<Dataset>();
     if (hipMalloc(reinterpret_cast<void **>(&ds->X), bytes) != hipSuccess)
-        return fail_msg(ESOM_ENOMEM, "dataset allocation failed");
+        return unreserve(ESOM_ENOMEM, "dataset allocation failed");
     if (hipMemcpy(ds->X, X_host, bytes, hipMemcpyHostToDevice) != hipSuccess) {
         (void)hipFree(ds->X);
-        return fail_msg(ESOM_EDEVICE, "dataset upload failed");
+        return unreserve(ESOM_EDEVICE, "dataset upload failed");
     }
     ds->n = n;
     ds->d = d;
     ds->bytes = bytes;
-    ds->id = S->next_id++;
-    S->resident += bytes;
-    *dataset_id = ds->id;
-    S->datasets[ds->id] = std::move(ds);
+    ds->id = id;
+    lk.lock();
+    *dataset_id = id;
+    S->datasets[id] = std::move(ds);
     return ESOM_OK;
 }
 
@@ -564,12 +576,10 @@ int esom_serve_submit(esom_server *S, uint64_t dataset_id, const float *X_host, 
     if (!S || !params || !L_hd_host || !L_2d_host || !out_host || !request_id)
         return fail_msg(ESOM_EINVAL, "NULL argument");
     const esom_params &P = *params;
-    if (g < 3 || g > ESOM_MAX_G) return fail_msg(ESOM_EINVAL, "g out of range");
-    if (P.k < 3 || P.k > g || P.k > ESOM_MAX_K) return fail_msg(ESOM_EINVAL, "k out of range");
-    if (!(P.boost > 0.f) || !(P.cutoff > 0.f) || !(P.gravity >= 0.f) ||
-        (P.mode != ESOM_MODE_FP32 && P.mode != ESOM_MODE_BF16_RESCORE) || P.candidates < 0 ||
-        P.candidates > g)
-        return fail_msg(ESOM_EINVAL, "bad parameters");
+    int vst = validate_params(P, g);
+    if (vst != ESOM_OK) return vst;
+    if (((uintptr_t)L_hd_host & 3u) || ((uintptr_t)L_2d_host & 3u) || ((uintptr_t)out_host & 3u))
+        return fail_msg(ESOM_EINVAL, "host arrays must be 4-byte aligned");
     auto r = std::make_unique<Request>();
     std::unique_lock<std::mutex> lk(S->mu);
     if (dataset_id) {
@@ -581,8 +591,10 @@ int esom_serve_submit(esom_server *S, uint64_t dataset_id, const float *X_host, 
         d = it->second->d;
         it->second->refs++;
     } else {
-        if (!X_host || n < 1 || d < 1 || d > ESOM_MAX_D)
-            return fail_msg(ESOM_EINVAL, "inline request needs X_host, n >= 1, 1 <= d <= ESOM_MAX_D");
+        if (!X_host || n < 1 || d < 1 || d > ESOM_MAX_D || n > (int64_t)INT32_MAX)
+            return fail_msg(ESOM_EINVAL,
+                            "inline request needs X_host, 1 <= n <= 2^31 - 1, 1 <= d <= ESOM_MAX_D");
+        if ((uintptr_t)X_host & 3u) return fail_msg(ESOM_EINVAL, "X_host must be 4-byte aligned");
     }
     r->dataset = dataset_id;
     r->Xh = X_host;

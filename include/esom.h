@@ -148,16 +148,20 @@ int esom_embed(esom_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
  *                     (2 sigma^2)) (sigma = 0: h_jb = [j == b]).
  *   L_hd     device, g x d floats, updated in place (stream-ordered)
  *   L_2d     device, g x 2 floats (read; may be NULL for kind 0)
- *   nearest  device, n int32 or NULL: b(i) from a previous esom_embed (its
- *            knn_idx[:, 0]); NULL = computed here exactly
+ *   nearest  device, n int32 at stride nearest_ld >= 1 (elements), or NULL:
+ *            b(i) from a previous esom_embed, e.g. its knn_idx with
+ *            nearest_ld = k (the first column); NULL = computed here exactly.
+ *            Entries outside [0, g) are ignored (the point counts nowhere).
  *   counts   device, g int32 or NULL: receives c_j
  * Sums and counts are accumulated in FP64, so the result does not depend on
  * the order in which points are visited beyond the final FP32 rounding.
  * Errors: ESOM_EINVAL for kind not 0/1, alpha not in [0,1], sigma < 0,
- * n < 0, d/g out of range, ldx < d, NULL required pointers. */
+ * n < 0, d/g out of range, ldx < d, nearest_ld < 1 with nearest given, NULL
+ * required pointers. */
 int esom_landmark_update(esom_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
                          float *L_hd, const float *L_2d, int32_t g, int32_t kind, float alpha,
-                         float sigma, const int32_t *nearest, int32_t *counts, void *stream);
+                         float sigma, const int32_t *nearest, int64_t nearest_ld, int32_t *counts,
+                         void *stream);
 
 /* Waits for the work enqueued on `stream`; ESOM_EDEVICE reports a device fault. */
 int esom_sync(esom_ctx *ctx, void *stream);
@@ -165,6 +169,19 @@ int esom_sync(esom_ctx *ctx, void *stream);
 /* Synchronises `stream`, then copies the context's counters into *stats
  * (host pointer); if reset != 0 the counters restart from zero. */
 int esom_get_stats(esom_ctx *ctx, void *stream, esom_stats *stats, int32_t reset);
+
+/* Diagnostics: the points that the last esom_embed (or landmark update
+ * computing its own nearest landmarks) on this context handed from the fast
+ * kernels to the exact FP64 path, in no particular order, with their reasons
+ * as bit flags (1: screen certificate failed, 2: near tie of distances FP32
+ * cannot order, 4: ill-conditioned system or nearly duplicate landmark pair,
+ * 8: degenerate neighbourhood).  Synchronises `stream` first.  Copies at most
+ * cap entries into the host arrays points / reasons (either may be NULL) and
+ * stores the full count in *count.  Shapes outside the fast kernels send every
+ * point to the exact path and list none (see n_slowpath).
+ * Errors: ESOM_EINVAL for NULL ctx or count, cap < 0. */
+int esom_get_fallback(esom_ctx *ctx, void *stream, int32_t *points, uint8_t *reasons, int64_t cap,
+                      int64_t *count);
 
 /* enable != 0: every following esom_embed on this context records HIP events
  * on its stream around the landmark preparation, the fused kernel and the

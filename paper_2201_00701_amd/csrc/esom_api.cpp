@@ -78,6 +78,9 @@ void dev_free(esom_ctx *c, void *&p, size_t bytes) {
     }
 }
 
+}  // namespace
+
+namespace esom {
 // Lays the embed scratch out for (n, g, dp) capacities; the pair table holds
 // pg x pg entries (0 when no call so far needed it).
 size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg) {
@@ -105,6 +108,9 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg) {
     sc.fb_thresh = static_cast<float *>(take(sizeof(float) * (size_t)(n > 0 ? n : 1)));
     return off;
 }
+}  // namespace esom
+
+namespace {
 
 int ensure_scratch(esom_ctx *c, int64_t n, int g, int dp, int pg, hipStream_t s) {
     if (c->arena && n <= c->cap_n && g <= c->cap_g && dp <= c->cap_dp && pg <= c->cap_pg) return ESOM_OK;
@@ -179,16 +185,20 @@ namespace esom {
 // Enqueues preparation + fast kernel + exact path.  what: EMBED_FULL,
 // EMBED_KNN_ONLY (k nearest only) or EMBED_PROJECT (scores/pairs/solve from
 // the given knn_idx / knn_d2).
-int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const float *L,
-              const float *l2d, int g, const esom_params &P, float *out, int32_t *knn_idx,
-              float *knn_d2, int what, hipStream_t s, uint8_t *knn_mark) {
-    const int knn_only = what == EMBED_KNN_ONLY;
+bool embed_needs_pairs(int d, int g, const esom_params &P, int what) {
     const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
     // the pair table is read only by the fast kernels' projection
-    const bool need_pairs = !knn_only && pl.kp != 0 && (what == EMBED_PROJECT || pl.fast);
-    int st = ensure_scratch(c, n, g, pl.dp, need_pairs ? g : 0, s);
-    if (st != ESOM_OK) return st;
-    Prep &pr = c->sc.prep;
+    return what != EMBED_KNN_ONLY && pl.kp != 0 && (what == EMBED_PROJECT || pl.fast);
+}
+
+int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t lds_per_block,
+                  const float *X, int64_t n, int d, int64_t ldx, const float *L, const float *l2d,
+                  int g, const esom_params &P, float *out, int32_t *knn_idx, float *knn_d2,
+                  int what, hipStream_t s, uint8_t *knn_mark, hipEvent_t *ev, int64_t chunk) {
+    const int knn_only = what == EMBED_KNN_ONLY;
+    const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
+    const bool need_pairs = embed_needs_pairs(d, g, P, what);
+    Prep &pr = sc.prep;
     pr.g = g;
     pr.d = d;
     pr.dp = pl.dp;
@@ -197,23 +207,14 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
     pr.npairs = pr.ntiles / 2;
     pr.mode = P.mode;
     pr.need_pairs = need_pairs ? 1 : 0;
-    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
-    const bool timed = c->timing && !knn_only;
-    if (timed) {
-        for (int i = 0; i < 4; ++i) {
-            hipError_t ee = hipEventCreate(&ev[i]);
-            if (ee != hipSuccess) return hip_fail(ee, "hipEventCreate");
-        }
-        (void)hipEventRecord(ev[0], s);
-    }
-    hipError_t e = launch_prep(pr, L, knn_only ? nullptr : l2d, P.mode, c->counters, knn_only ? 0 : (long long)n, s);
+    if (chunk <= 0 || chunk > n) chunk = n;
+    if (ev) (void)hipEventRecord(ev[0], s);
+    hipError_t e = launch_prep(pr, L, knn_only ? nullptr : l2d, P.mode, counters, knn_only ? 0 : (long long)n, s);
     if (e != hipSuccess) return hip_fail(e, "landmark preparation launch");
-    if (timed) (void)hipEventRecord(ev[1], s);
+    if (ev) (void)hipEventRecord(ev[1], s);
 
     EmbedArgs a;
     memset(&a, 0, sizeof a);
-    a.X = X;
-    a.n = n;
     a.ldx = ldx;
     a.d = d;
     a.dp = pl.dp;
@@ -238,39 +239,75 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
     a.gravity = P.gravity;
     a.adjust = P.adjust;
     a.Wk = (float)harmonic(P.k);
-    a.out = out;
-    a.knn_idx = knn_idx;
-    a.knn_d2 = knn_d2;
-    a.fb_list = c->sc.fb_list;
-    a.fb_reason = c->sc.fb_reason;
-    a.fb_thresh = c->sc.fb_thresh;
-    a.counters = c->counters;
+    a.fb_list = sc.fb_list;
+    a.fb_reason = sc.fb_reason;
+    a.fb_thresh = sc.fb_thresh;
+    a.counters = counters;
     a.knn_only = knn_only;
-    a.knn_mark = knn_mark;
-    a.x_vec4 = (d == pl.dp && ldx % 4 == 0 && ((uintptr_t)X & 15) == 0 &&
-                ((uintptr_t)pr.cent & 15) == 0) ? 1 : 0;
-    if (what == EMBED_PROJECT && pl.kp != 0) {
-        e = launch_project(a, pl.kp, c->num_cus, s);
-        if (e != hipSuccess) return hip_fail(e, "projection kernel launch");
-        if (timed) (void)hipEventRecord(ev[2], s);
-        e = launch_fallback(a, c->num_cus, c->lds_per_block, s);
-        if (e != hipSuccess) return hip_fail(e, "exact-path launch");
-    } else if (pl.fast) {
-        e = launch_embed(a, P.mode, pl.kp, c->num_cus, c->lds_per_block, s);
-        if (e != hipSuccess) return hip_fail(e, "embed kernel launch");
-        if (timed) (void)hipEventRecord(ev[2], s);
-        e = launch_fallback(a, c->num_cus, c->lds_per_block, s);
-        if (e != hipSuccess) return hip_fail(e, "exact-path launch");
-    } else {
-        if (timed) (void)hipEventRecord(ev[2], s);
-        e = launch_all_to_fallback(a, c->num_cus, c->lds_per_block, s);
-        if (e != hipSuccess) return hip_fail(e, "exact-path launch");
+    // Points go in chunks of at most `chunk` (the fallback list's capacity):
+    // each chunk is screened, then its listed points are recomputed, before
+    // the next chunk reuses the list.
+    for (int64_t c0 = 0; c0 < n; c0 += chunk) {
+        const int64_t m = n - c0 < chunk ? n - c0 : chunk;
+        if (c0 > 0) {
+            e = launch_reset_fallback(counters, s);
+            if (e != hipSuccess) return hip_fail(e, "counter reset launch");
+        }
+        a.X = X + c0 * ldx;
+        a.n = m;
+        a.out = out ? out + 2 * c0 : nullptr;
+        a.knn_idx = knn_idx ? knn_idx + c0 * P.k : nullptr;
+        a.knn_d2 = knn_d2 ? knn_d2 + c0 * P.k : nullptr;
+        a.knn_mark = knn_mark ? knn_mark + c0 : nullptr;
+        a.x_vec4 = (d == pl.dp && ldx % 4 == 0 && ((uintptr_t)a.X & 15) == 0 &&
+                    ((uintptr_t)pr.cent & 15) == 0) ? 1 : 0;
+        const bool last = c0 + m >= n;
+        if (what == EMBED_PROJECT && pl.kp != 0) {
+            e = launch_project(a, pl.kp, num_cus, s);
+            if (e != hipSuccess) return hip_fail(e, "projection kernel launch");
+            if (ev && last) (void)hipEventRecord(ev[2], s);
+            e = launch_fallback(a, num_cus, lds_per_block, s);
+            if (e != hipSuccess) return hip_fail(e, "exact-path launch");
+        } else if (pl.fast) {
+            e = launch_embed(a, P.mode, pl.kp, num_cus, lds_per_block, s);
+            if (e != hipSuccess) return hip_fail(e, "embed kernel launch");
+            if (ev && last) (void)hipEventRecord(ev[2], s);
+            e = launch_fallback(a, num_cus, lds_per_block, s);
+            if (e != hipSuccess) return hip_fail(e, "exact-path launch");
+        } else {
+            if (ev && last) (void)hipEventRecord(ev[2], s);
+            e = launch_all_to_fallback(a, num_cus, lds_per_block, s);
+            if (e != hipSuccess) return hip_fail(e, "exact-path launch");
+        }
     }
-    if (timed) {
-        (void)hipEventRecord(ev[3], s);
-        for (int i = 0; i < 4; ++i) c->pending.push_back(ev[i]);
-    }
+    if (ev) (void)hipEventRecord(ev[3], s);
     return ESOM_OK;
+}
+
+int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const float *L,
+              const float *l2d, int g, const esom_params &P, float *out, int32_t *knn_idx,
+              float *knn_d2, int what, hipStream_t s, uint8_t *knn_mark) {
+    const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
+    int st = ensure_scratch(c, n, g, pl.dp, embed_needs_pairs(d, g, P, what) ? g : 0, s);
+    if (st != ESOM_OK) return st;
+    hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
+    const bool timed = c->timing && what != EMBED_KNN_ONLY;
+    if (timed) {
+        for (int i = 0; i < 4; ++i) {
+            hipError_t ee = hipEventCreate(&ev[i]);
+            if (ee != hipSuccess) return hip_fail(ee, "hipEventCreate");
+        }
+    }
+    st = enqueue_embed(c->sc, c->counters, c->num_cus, c->lds_per_block, X, n, d, ldx, L, l2d, g, P,
+                       out, knn_idx, knn_d2, what, s, knn_mark, timed ? ev : nullptr, n);
+    if (timed) {
+        if (st == ESOM_OK) {
+            for (int i = 0; i < 4; ++i) c->pending.push_back(ev[i]);
+        } else {
+            for (int i = 0; i < 4; ++i) (void)hipEventDestroy(ev[i]);
+        }
+    }
+    return st;
 }
 
 size_t ctx_held_bytes(const esom_ctx *c) { return c->held; }
@@ -287,6 +324,22 @@ size_t embed_scratch_bytes(int64_t n, int g, int d) {
 }
 
 int fail_msg(int code, const char *msg) { return fail(code, "%s", msg); }
+
+int validate_embed(const float *X, int64_t n, int d, int64_t ldx, const float *L_hd,
+                   const float *L_2d, int g, const esom_params &P, const float *out,
+                   const int32_t *knn_idx, const float *knn_dist2) {
+    int st = validate_common(X, n, d, ldx, L_hd, g);
+    if (st != ESOM_OK) return st;
+    st = validate_params(P, g);
+    if (st != ESOM_OK) return st;
+    if (!L_2d || !aligned4(L_2d)) return fail(ESOM_EINVAL, "L_2d is NULL or not 4-byte aligned");
+    if (n > 0 && (!out || ((uintptr_t)out & 7u)))
+        return fail(ESOM_EINVAL, "out is NULL or not 8-byte aligned");
+    if ((knn_idx && !aligned4(knn_idx)) || (knn_dist2 && !aligned4(knn_dist2)))
+        return fail(ESOM_EINVAL, "knn outputs must be 4-byte aligned");
+    if (((uintptr_t)L_2d & 7u)) return fail(ESOM_EINVAL, "L_2d must be 8-byte aligned");
+    return ESOM_OK;
+}
 
 int validate_params(const esom_params &P, int g) {
     if (g < 3 || g > ESOM_MAX_G) return fail(ESOM_EINVAL, "g = %d outside [3, %d]", g, ESOM_MAX_G);
@@ -361,6 +414,31 @@ int esom_create(int device, size_t hbm_budget_bytes, esom_ctx **out) {
     return ESOM_OK;
 }
 
+int esom_get_fallback(esom_ctx *c, void *stream, int32_t *points, uint8_t *reasons, int64_t cap,
+                      int64_t *count) {
+    t_err.clear();
+    if (!c || !count) return fail(ESOM_EINVAL, "ctx or count is NULL");
+    if (cap < 0) return fail(ESOM_EINVAL, "cap = %lld < 0", (long long)cap);
+    int st = esom_sync(c, stream);
+    if (st != ESOM_OK) return st;
+    unsigned long long len = 0;
+    hipError_t e = hipMemcpy(&len, c->counters + C_FB_LEN, sizeof len, hipMemcpyDeviceToHost);
+    if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    if (!c->arena) len = 0;
+    if (len > (unsigned long long)c->cap_n) len = (unsigned long long)c->cap_n;
+    *count = (int64_t)len;
+    const size_t m = (size_t)((int64_t)len < cap ? (int64_t)len : cap);
+    if (m && points) {
+        e = hipMemcpy(points, c->sc.fb_list, m * sizeof(int32_t), hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    }
+    if (m && reasons) {
+        e = hipMemcpy(reasons, c->sc.fb_reason, m, hipMemcpyDeviceToHost);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpy");
+    }
+    return ESOM_OK;
+}
+
 int esom_set_timing(esom_ctx *c, int32_t enable) {
     t_err.clear();
     if (!c) return fail(ESOM_EINVAL, "ctx is NULL");
@@ -387,17 +465,10 @@ int esom_embed(esom_ctx *c, const float *X, int64_t n, int32_t d, int64_t ldx, c
     t_err.clear();
     if (!c) return fail(ESOM_EINVAL, "ctx is NULL");
     if (!params) return fail(ESOM_EINVAL, "params is NULL");
-    int st = validate_common(X, n, d, ldx, L_hd, g);
-    if (st != ESOM_OK) return st;
+    int st;
     const esom_params &P = *params;
-    st = validate_params(P, g);
+    st = validate_embed(X, n, d, ldx, L_hd, L_2d, g, P, out, knn_idx, knn_dist2);
     if (st != ESOM_OK) return st;
-    if (!L_2d || !aligned4(L_2d)) return fail(ESOM_EINVAL, "L_2d is NULL or not 4-byte aligned");
-    if (n > 0 && (!out || ((uintptr_t)out & 7u)))
-        return fail(ESOM_EINVAL, "out is NULL or not 8-byte aligned");
-    if ((knn_idx && !aligned4(knn_idx)) || (knn_dist2 && !aligned4(knn_dist2)))
-        return fail(ESOM_EINVAL, "knn outputs must be 4-byte aligned");
-    if (((uintptr_t)L_2d & 7u)) return fail(ESOM_EINVAL, "L_2d must be 8-byte aligned");
     if (n == 0) return ESOM_OK;
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
@@ -407,7 +478,8 @@ int esom_embed(esom_ctx *c, const float *X, int64_t n, int32_t d, int64_t ldx, c
 
 int esom_landmark_update(esom_ctx *c, const float *X, int64_t n, int32_t d, int64_t ldx,
                          float *L_hd, const float *L_2d, int32_t g, int32_t kind, float alpha,
-                         float sigma, const int32_t *nearest, int32_t *counts, void *stream) {
+                         float sigma, const int32_t *nearest, int64_t nearest_ld, int32_t *counts,
+                         void *stream) {
     t_err.clear();
     if (!c) return fail(ESOM_EINVAL, "ctx is NULL");
     int st = validate_common(X, n, d, ldx, L_hd, g);
@@ -419,10 +491,12 @@ int esom_landmark_update(esom_ctx *c, const float *X, int64_t n, int32_t d, int6
         return fail(ESOM_EINVAL, "L_2d is required (4-byte aligned) for the SOM update");
     if ((nearest && !aligned4(nearest)) || (counts && !aligned4(counts)))
         return fail(ESOM_EINVAL, "nearest/counts must be 4-byte aligned");
+    if (nearest && nearest_ld < 1) return fail(ESOM_EINVAL, "nearest_ld = %lld < 1", (long long)nearest_ld);
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     hipStream_t s = static_cast<hipStream_t>(stream);
     const int32_t *near = nearest;
+    int64_t near_ld = nearest ? nearest_ld : 1;
     if (!near && n > 0) {
         if (n > c->nearest_cap) {
             if (c->nearest) {
@@ -469,6 +543,7 @@ int esom_landmark_update(esom_ctx *c, const float *X, int64_t n, int32_t d, int6
     u.L = L_hd;
     u.l2d = L_2d;
     u.nearest = near;
+    u.nearest_ld = near_ld;
     u.counts = counts;
     e = launch_update(u, c->uws, c->num_cus, s);
     if (e != hipSuccess) return hip_fail(e, "landmark update launch");
@@ -520,7 +595,8 @@ int esom_get_stats(esom_ctx *c, void *stream, esom_stats *stats, int32_t reset) 
     if (reset) {
         c->n_timed = 0;
         c->ms_prep = c->ms_main = c->ms_exact = 0.0;
-        e = hipMemset(c->counters, 0, sizeof h);
+        // all but the last call's fallback-list length (esom_get_fallback reads it)
+        e = hipMemset(c->counters + C_POINTS, 0, sizeof h - C_POINTS * sizeof(unsigned long long));
         if (e != hipSuccess) return hip_fail(e, "hipMemset");
         e = hipDeviceSynchronize();
         if (e != hipSuccess) return hip_fail(e, "hipDeviceSynchronize");

@@ -751,6 +751,15 @@ hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, size_t lds_pe
     return hipGetLastError();
 }
 
+__global__ void reset_fallback(unsigned long long *counters) {
+    if (threadIdx.x == 0) counters[C_FB_LEN] = 0ull;
+}
+
+hipError_t launch_reset_fallback(unsigned long long *counters, hipStream_t s) {
+    hipLaunchKernelGGL(reset_fallback, dim3(1), dim3(64), 0, s, counters);
+    return hipGetLastError();
+}
+
 // ---------------------------------------------------------------- projection from given neighbours
 
 hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s) {

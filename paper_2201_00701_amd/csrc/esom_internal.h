@@ -108,6 +108,8 @@ hipError_t launch_embed(const EmbedArgs &a, int mode, int kp, int num_cus, size_
 hipError_t launch_fallback(const EmbedArgs &a, int num_cus, size_t lds_per_block, hipStream_t s);
 hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s);
 hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, size_t lds_per_block, hipStream_t s);
+// Resets the fallback-list length (counters[C_FB_LEN]) with a one-thread kernel.
+hipError_t launch_reset_fallback(unsigned long long *counters, hipStream_t s);
 
 // Landmark update (esom_update.hip).
 struct UpdateArgs {
@@ -118,6 +120,7 @@ struct UpdateArgs {
     float *L;
     const float *l2d;
     const int32_t *nearest;
+    int64_t nearest_ld;  // element stride of nearest
     int32_t *counts;
 };
 size_t update_workspace_bytes(int64_t n, int g, int d);
@@ -128,11 +131,28 @@ enum EmbedWhat { EMBED_FULL = 0, EMBED_KNN_ONLY = 1, EMBED_PROJECT = 2 };
 int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const float *L,
               const float *l2d, int g, const esom_params &P, float *out, int32_t *knn_idx,
               float *knn_d2, int what, hipStream_t s, uint8_t *knn_mark = nullptr);
+// The launch sequence of one embed on the given scratch (laid out by carve for
+// at least min(n, chunk) points) and counters: landmark preparation, then per
+// chunk of at most `chunk` points (chunk <= 0: all) the fast kernel and the
+// exact path.  ev: 4 events recorded around the phases, or NULL.  Allocates nothing.
+int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t lds_per_block,
+                  const float *X, int64_t n, int d, int64_t ldx, const float *L, const float *l2d,
+                  int g, const esom_params &P, float *out, int32_t *knn_idx, float *knn_d2,
+                  int what, hipStream_t s, uint8_t *knn_mark, hipEvent_t *ev, int64_t chunk);
+// Whether an embed of this shape reads the g x g pair table.
+bool embed_needs_pairs(int d, int g, const esom_params &P, int what);
+// Lays out an embed scratch at base (NULL: only sizes it) for n points, g
+// landmarks, padded dimension dp and a pg x pg pair table; returns its bytes.
+size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg);
 size_t ctx_held_bytes(const esom_ctx *c);
 void ctx_trim(esom_ctx *c);
 size_t embed_scratch_bytes(int64_t n, int g, int d);
 int fail_msg(int code, const char *msg);
 // Checks the parameters of an embed over g landmarks (the esom_embed rules).
 int validate_params(const esom_params &P, int g);
+// Checks every esom_embed argument (shapes, parameters, pointers, alignment).
+int validate_embed(const float *X, int64_t n, int d, int64_t ldx, const float *L_hd,
+                   const float *L_2d, int g, const esom_params &P, const float *out,
+                   const int32_t *knn_idx, const float *knn_dist2);
 
 }  // namespace esom

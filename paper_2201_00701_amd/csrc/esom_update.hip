@@ -19,7 +19,7 @@ constexpr int UPD_BLOCK = 256;
 constexpr int UPD_CHUNK = 4096;  // points per histogram block / per summing chunk
 
 // counts[j] += number of points whose nearest landmark is j.
-__global__ void upd_hist(const int32_t *__restrict__ nearest, int64_t n, int g,
+__global__ void upd_hist(const int32_t *__restrict__ nearest, int64_t ld, int64_t n, int g,
                          int *__restrict__ counts) {
     extern __shared__ int hist[];
     for (int j = threadIdx.x; j < g; j += blockDim.x) hist[j] = 0;
@@ -27,7 +27,7 @@ __global__ void upd_hist(const int32_t *__restrict__ nearest, int64_t n, int g,
     const int64_t b0 = (int64_t)blockIdx.x * UPD_CHUNK;
     const int64_t b1 = b0 + UPD_CHUNK < n ? b0 + UPD_CHUNK : n;
     for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-        const int j = nearest[i];
+        const int j = nearest[i * ld];
         if (j >= 0 && j < g) atomicAdd(&hist[j], 1);  // invalid indices are ignored
     }
     __syncthreads();
@@ -49,7 +49,7 @@ __global__ void upd_scan(const int *__restrict__ counts, int g, int64_t *__restr
 }
 
 // Scatter point indices into their landmark's range.
-__global__ void upd_scatter(const int32_t *__restrict__ nearest, int64_t n, int g,
+__global__ void upd_scatter(const int32_t *__restrict__ nearest, int64_t ld, int64_t n, int g,
                             unsigned long long *__restrict__ cursor, int32_t *__restrict__ perm) {
     extern __shared__ int sh[];
     int *hist = sh;                                               // g: block histogram
@@ -60,7 +60,7 @@ __global__ void upd_scatter(const int32_t *__restrict__ nearest, int64_t n, int 
     const int64_t b0 = (int64_t)blockIdx.x * UPD_CHUNK;
     const int64_t b1 = b0 + UPD_CHUNK < n ? b0 + UPD_CHUNK : n;
     for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-        const int j = nearest[i];
+        const int j = nearest[i * ld];
         if (j >= 0 && j < g) atomicAdd(&hist[j], 1);
     }
     __syncthreads();
@@ -70,7 +70,7 @@ __global__ void upd_scatter(const int32_t *__restrict__ nearest, int64_t n, int 
     }
     __syncthreads();
     for (int64_t i = b0 + threadIdx.x; i < b1; i += blockDim.x) {
-        const int j = nearest[i];
+        const int j = nearest[i * ld];
         if (j < 0 || j >= g) continue;
         const int pos = atomicAdd(&base[j], 1);
         perm[claim[j] + pos] = (int32_t)i;
@@ -225,13 +225,13 @@ hipError_t launch_update(const UpdateArgs &u, void *ws, int num_cus, hipStream_t
     const unsigned hblocks = (unsigned)((u.n + UPD_CHUNK - 1) / UPD_CHUNK);
     if (u.n > 0) {
         hipLaunchKernelGGL(upd_hist, dim3(hblocks), dim3(UPD_BLOCK), sizeof(int) * u.g, s, u.nearest,
-                           u.n, u.g, counts);
+                           u.nearest_ld, u.n, u.g, counts);
     }
     hipLaunchKernelGGL(upd_scan, dim3(1), dim3(64), 0, s, counts, u.g, offsets, cursor);
     if (u.n > 0) {
         const size_t sh = sizeof(int) * 2 * (size_t)u.g + sizeof(long long) * (size_t)u.g;
-        hipLaunchKernelGGL(upd_scatter, dim3(hblocks), dim3(UPD_BLOCK), sh, s, u.nearest, u.n, u.g,
-                           cursor, perm);
+        hipLaunchKernelGGL(upd_scatter, dim3(hblocks), dim3(UPD_BLOCK), sh, s, u.nearest, u.nearest_ld,
+                           u.n, u.g, cursor, perm);
         hipLaunchKernelGGL(upd_chunks, dim3(1), dim3(64), 0, s, counts, u.g, chunk_landmark,
                            chunk_start, nchunks);
         // Grid sized for the worst case; blocks past the chunk count exit at once.

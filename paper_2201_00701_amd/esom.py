@@ -98,12 +98,14 @@ def load(path: str = LIB_PATH):
                                ctypes.POINTER(esom_params), _vp, _vp, _vp, _vp]
     lib.esom_embed.restype = ctypes.c_int
     lib.esom_landmark_update.argtypes = [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32, _f32,
-                                         _f32, _vp, _vp, _vp]
+                                         _f32, _vp, _i64, _vp, _vp]
     lib.esom_landmark_update.restype = ctypes.c_int
     lib.esom_sync.argtypes = [_vp, _vp]
     lib.esom_sync.restype = ctypes.c_int
     lib.esom_get_stats.argtypes = [_vp, _vp, ctypes.POINTER(esom_stats), _i32]
     lib.esom_get_stats.restype = ctypes.c_int
+    lib.esom_get_fallback.argtypes = [_vp, _vp, _vp, _vp, _i64, ctypes.POINTER(_i64)]
+    lib.esom_get_fallback.restype = ctypes.c_int
     lib.esom_set_timing.argtypes = [_vp, _i32]
     lib.esom_set_timing.restype = ctypes.c_int
     u64p = ctypes.POINTER(ctypes.c_uint64)
@@ -170,9 +172,10 @@ def esom_embed(ctx, X, n, d, ldx, L_hd, L_2d, g, params, out, knn_idx=0, knn_dis
 
 
 def esom_landmark_update(ctx, X, n, d, ldx, L_hd, L_2d, g, kind, alpha, sigma, nearest=0,
-                         counts=0, stream=0) -> int:
+                         nearest_ld=1, counts=0, stream=0) -> int:
     return load().esom_landmark_update(ctx, X, n, d, ldx, L_hd, L_2d or None, g, kind, alpha,
-                                       sigma, nearest or None, counts or None, stream or None)
+                                       sigma, nearest or None, nearest_ld, counts or None,
+                                       stream or None)
 
 
 def esom_sync(ctx, stream=0) -> int:
@@ -183,6 +186,14 @@ def esom_get_stats(ctx, stream=0, reset=False) -> dict:
     st = esom_stats()
     _check(load().esom_get_stats(ctx, stream or None, ctypes.byref(st), 1 if reset else 0))
     return st.as_dict()
+
+
+def esom_get_fallback(ctx, stream=0, points=0, reasons=0, cap=0):
+    """Returns (status, count); points / reasons are host addresses (or 0)."""
+    cnt = _i64()
+    rc = load().esom_get_fallback(ctx, stream or None, points or None, reasons or None, cap,
+                                  ctypes.byref(cnt))
+    return rc, cnt.value
 
 
 def esom_set_timing(ctx, enable=True) -> int:
@@ -261,13 +272,14 @@ class Context:
         g = L.shape[0]
         lp = _dev_f32(l, "l", 2).contiguous().data_ptr() if l is not None else 0
         cnt = torch.empty(g, dtype=torch.int32, device=X.device) if counts else None
-        np_ = 0
+        np_, nld = 0, 1
         if nearest is not None:
-            if nearest.dtype != torch.int32 or not nearest.is_contiguous():
-                raise TypeError("nearest must be a contiguous int32 tensor")
-            np_ = nearest.data_ptr()
+            # a 1-D int32 tensor of n entries at any stride (e.g. knn_idx[:, 0])
+            if nearest.dtype != torch.int32 or nearest.dim() != 1 or nearest.shape[0] != n:
+                raise TypeError("nearest must be a 1-D int32 tensor of n entries")
+            np_, nld = nearest.data_ptr(), nearest.stride(0)
         _check(esom_landmark_update(self.handle, X.data_ptr(), n, d, X.stride(0), L.data_ptr(), lp,
-                                    g, {"kmeans": 0, "som": 1}[kind], alpha, sigma, np_,
+                                    g, {"kmeans": 0, "som": 1}[kind], alpha, sigma, np_, nld,
                                     cnt.data_ptr() if counts else 0, self._stream(stream)))
         return cnt
 
@@ -279,6 +291,18 @@ class Context:
 
     def stats(self, reset=False, stream=None):
         return esom_get_stats(self.handle, self._stream(stream), reset)
+
+    def fallback(self, stream=None):
+        """(points int32, reasons uint8): the last call's exact-path list."""
+        import numpy as np
+        rc, n = esom_get_fallback(self.handle, self._stream(stream))
+        _check(rc)
+        pts = np.empty(n, np.int32)
+        rsn = np.empty(n, np.uint8)
+        rc, n2 = esom_get_fallback(self.handle, self._stream(stream), pts.ctypes.data,
+                                   rsn.ctypes.data, n)
+        _check(rc)
+        return pts[:min(n, n2)], rsn[:min(n, n2)]
 
 
 # ---- serving (host arrays) ----------------------------------------------------------

@@ -157,3 +157,51 @@ def test_drop_while_in_flight_and_unknown_ids(torch_dev):
     rc, _ = esom.esom_serve_wait(srv.handle, 987654321, 0)
     assert rc == esom.ESOM_ENOTFOUND
     srv.close()
+
+
+def test_resident_nan_row_cache_hit(torch_dev):
+    # a non-finite row gets index -1 in the k-nearest cache; the next 2-D edit
+    # projects from the cache: that row must go to the exact path again (NaN
+    # output, no out-of-range loads) and every other row must equal a direct call
+    from paper_2201_00701_amd.esom import Server
+    X, L, l = _req(311, 5000, 16, 100, 10)
+    X = X.copy()
+    X[17, 3] = np.nan
+    srv = Server(0, 0, 2)
+    did = srv.put(X)
+    _say("case serve resident dataset with a NaN row")
+    out1 = np.empty((len(X), 2), np.float32)
+    info1 = srv.wait(srv.submit(L, l, k=8, mode="bf16", dataset=did, out=out1), 60000)
+    l2 = l.copy()
+    l2[5] += 0.3
+    out2 = np.empty((len(X), 2), np.float32)
+    info2 = srv.wait(srv.submit(L, l2, k=8, mode="bf16", dataset=did, out=out2), 60000)
+    assert info1["cache_hit"] == 0 and info2["cache_hit"] == 1
+    ok = np.arange(len(X)) != 17
+    np.testing.assert_array_equal(out1[ok], _direct(torch_dev, X, L, l, 8, "bf16")[ok])
+    np.testing.assert_array_equal(out2[ok], _direct(torch_dev, X, L, l2, 8, "bf16")[ok])
+    assert np.all(np.isnan(out1[17])) and np.all(np.isnan(out2[17]))
+    srv.close()
+
+
+def test_submit_rejections(torch_dev):
+    # the same argument rules as esom_embed, checked before anything is queued
+    from paper_2201_00701_amd import esom
+    from paper_2201_00701_amd.esom import Server
+    X, L, l = _req(321, 500, 8, 50, 10)
+    srv = Server(0, 0, 1)
+    _say("case serve submit rejections")
+    bad = [dict(k=2), dict(k=51), dict(boost=0.0), dict(boost=50.0), dict(cutoff=0.0),
+           dict(cutoff=float("inf")), dict(gravity=-1.0), dict(gravity=float("nan")),
+           dict(adjust=float("inf")), dict(mode=5), dict(candidates=51)]
+    for kw in bad:
+        p = {"k": 8, **kw}
+        with pytest.raises(esom.EsomError) as e:
+            srv.submit(L, l, X=X, **p)
+        assert e.value.code == esom.ESOM_EINVAL, kw
+    st = srv.stats()
+    assert st["queued"] == 0 and st["completed"] == 0
+    # and a valid request still runs
+    info = srv.wait(srv.submit(L, l, k=8, X=X), 60000)
+    np.testing.assert_array_equal(info["out"], _direct(torch_dev, X, L, l, 8, "fp32"))
+    srv.close()

@@ -59,6 +59,12 @@ def _load():
         lib.oracle_landmark_update.argtypes = [f32p, i64, i32, i64, f32p, f32p, i32, i32,
                                                dbl, dbl, f64p, i64p, i32]
         lib.oracle_landmark_update.restype = i32
+        u8p = ctypes.POINTER(ctypes.c_uint8)
+        lib.oracle_som_train.argtypes = [f32p, i64, i32, i64, f32p, f32p, i32, i32p, i32, i32,
+                                         f64p, f64p, u8p]
+        lib.oracle_som_train.restype = i32
+        lib.oracle_fit_landmarks.argtypes = [f32p, f32p, i32, i32, f32p, i32, i32, dbl, f64p]
+        lib.oracle_fit_landmarks.restype = i32
         _lib = lib
     return _lib
 
@@ -150,3 +156,47 @@ def landmark_update(X, L, l, kind, alpha, sigma=0.0, threads=1):
     if rc != 0:
         raise ValueError("oracle_landmark_update failed (%d)" % rc)
     return Lout, counts
+
+
+def som_train(X, L, l, batch_idx, sigma, alpha, frozen=None):
+    """Online SOM training steps (mini-batch form of the online rule).  batch_idx
+    is T x B int32 (rows of X per step); sigma, alpha have T entries.  Returns
+    the trained landmarks (float32 g x d, a new array)."""
+    lib = _load()
+    X, ldx = _f32_rows(X)
+    Lw = np.array(L, dtype=np.float32, order="C", copy=True)
+    l = np.ascontiguousarray(l, dtype=np.float32)
+    bi = np.ascontiguousarray(batch_idx, dtype=np.int32)
+    T, B = bi.shape
+    sg = np.ascontiguousarray(sigma, dtype=np.float64)
+    al = np.ascontiguousarray(alpha, dtype=np.float64)
+    if sg.shape != (T,) or al.shape != (T,):
+        raise ValueError("sigma and alpha need one entry per step")
+    fz = None
+    if frozen is not None:
+        fz = np.ascontiguousarray(frozen, dtype=np.uint8)
+    n, d = X.shape
+    rc = lib.oracle_som_train(_ptr(X, ctypes.c_float), n, d, ldx, _ptr(Lw, ctypes.c_float),
+                              _ptr(l, ctypes.c_float), len(Lw), _ptr(bi, ctypes.c_int32), B, T,
+                              _ptr(sg, ctypes.c_double), _ptr(al, ctypes.c_double),
+                              _ptr(fz, ctypes.c_uint8) if fz is not None else None)
+    if rc != 0:
+        raise ValueError("oracle_som_train failed (%d)" % rc)
+    return Lw
+
+
+def fit_landmarks(L, l, p, kfit=8, sigma=1.0):
+    """High-dimensional positions (m x d float64) of landmarks added at the 2-D
+    positions p (m x 2), fitted from their kfit nearest 2-D landmarks."""
+    lib = _load()
+    L = np.ascontiguousarray(L, dtype=np.float32)
+    l = np.ascontiguousarray(l, dtype=np.float32)
+    p = np.ascontiguousarray(p, dtype=np.float32).reshape(-1, 2)
+    g, d = L.shape
+    out = np.empty((len(p), d), np.float64)
+    rc = lib.oracle_fit_landmarks(_ptr(L, ctypes.c_float), _ptr(l, ctypes.c_float), g, d,
+                                  _ptr(p, ctypes.c_float), len(p), int(kfit), float(sigma),
+                                  _ptr(out, ctypes.c_double))
+    if rc != 0:
+        raise ValueError("oracle_fit_landmarks failed (%d)" % rc)
+    return out

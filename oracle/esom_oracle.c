@@ -424,3 +424,175 @@ int oracle_landmark_update(const float *X, int64_t n, int d, int64_t ldx,
     free(nearest); free(nd); free(S); free(c);
     return st;
 }
+
+/* ---- online SOM training and new-landmark fitting -------------------------- */
+
+/* Supervised SOM training (Section "Supervised training of self-organizing
+ * maps"): the 2-D landmarks l are the map topology and the high-dimensional
+ * landmarks L are the neuron weights, trained with the user's neighbourhood
+ * size sigma and learning rate alpha, which may change from step to step.
+ * Kohonen's online rule moves every landmark towards a presented point x by
+ * alpha h(j, b) (x - L_j), b the point's best-matching (nearest) landmark and
+ * h(j, b) = exp(-|l_j - l_b|^2 / (2 sigma^2)) (h = [j == b] for sigma = 0).
+ * One step here presents a batch of B points (rows batch_idx[t*B .. t*B+B-1]
+ * of X), finds every point's best-matching landmark against the step's
+ * landmarks, and applies the average of the B single-point updates:
+ *   L_j <- L_j + (alpha_t / B) sum_i h(j, b_i) (x_i - L_j).
+ * With B = 1 this is the serial online rule.  Landmarks with frozen[j] != 0
+ * keep their position (they still match points).  The landmarks are stored
+ * as float32 between steps, as the caller's array is.  Batch entries outside
+ * [0, n) present no point (they still count in B). */
+int oracle_som_train(const float *X, int64_t n, int d, int64_t ldx, float *L, const float *l,
+                     int g, const int32_t *batch_idx, int B, int T, const double *sigma,
+                     const double *alpha, const uint8_t *frozen)
+{
+    if (n < 0 || d < 1 || g < 1 || B < 1 || T < 0 || ldx < d || !X || !L || !l || !batch_idx ||
+        !sigma || !alpha)
+        return ORACLE_EINVAL;
+    int *bmu = (int *)malloc(sizeof(int) * (size_t)B);
+    double *delta = (double *)malloc(sizeof(double) * (size_t)g * d);
+    if (!bmu || !delta) {
+        free(bmu); free(delta);
+        return ORACLE_ENOMEM;
+    }
+    for (int t = 0; t < T; ++t) {
+        const int32_t *rows = batch_idx + (size_t)t * B;
+        /* best-matching landmarks against this step's landmarks */
+        for (int i = 0; i < B; ++i) {
+            bmu[i] = -1;
+            if (rows[i] < 0 || rows[i] >= n)
+                continue;
+            double d2;
+            nearest_m(X + (int64_t)rows[i] * ldx, L, g, d, 1, &bmu[i], &d2);
+        }
+        /* the average of the single-point updates */
+        for (int j = 0; j < g; ++j) {
+            double *dj = delta + (size_t)j * d;
+            for (int c = 0; c < d; ++c)
+                dj[c] = 0.0;
+            for (int i = 0; i < B; ++i) {
+                int b = bmu[i];
+                if (b < 0)
+                    continue;
+                double h;
+                if (sigma[t] == 0.0) {
+                    h = (b == j) ? 1.0 : 0.0;
+                } else {
+                    double dx = (double)l[2 * j] - (double)l[2 * b];
+                    double dy = (double)l[2 * j + 1] - (double)l[2 * b + 1];
+                    h = exp(-(dx * dx + dy * dy) / (2.0 * sigma[t] * sigma[t]));
+                }
+                const float *x = X + (int64_t)rows[i] * ldx;
+                for (int c = 0; c < d; ++c)
+                    dj[c] += h * ((double)x[c] - (double)L[(size_t)j * d + c]);
+            }
+        }
+        for (int j = 0; j < g; ++j) {
+            if (frozen && frozen[j])
+                continue;
+            for (int c = 0; c < d; ++c) {
+                double v = (double)L[(size_t)j * d + c] + alpha[t] / (double)B * delta[(size_t)j * d + c];
+                L[(size_t)j * d + c] = (float)v;
+            }
+        }
+    }
+    free(bmu); free(delta);
+    return ORACLE_OK;
+}
+
+/* High-dimensional position of a landmark added at 2-D position p (Section
+ * "Supervised training of self-organizing maps": fitted from the landmarks
+ * that are close in 2-D).  The kfit landmarks nearest to p in 2-D (by
+ * (squared distance, index)) get weights w_j = exp(-|l_j - p|^2 / (2 sigma^2)),
+ * here scaled by a common factor so that the nearest one weighs 1 (neither the
+ * fit nor the mean depends on a common factor, and no weight underflows);
+ * an affine map z -> A z + c from 2-D to the high-dimensional space is fitted
+ * to them by weighted least squares, min sum_j w_j |L_j - A l_j - c|^2, and
+ * evaluated at p.  When the neighbours do not determine an affine map (fewer
+ * than three, or collinear: det of the 3 x 3 normal matrix <= 1e-12 times the
+ * cube of its mean diagonal), the weighted mean of their L_j is used. */
+int oracle_fit_landmarks(const float *L, const float *l, int g, int d, const float *p, int m,
+                         int kfit, double sigma, double *out)
+{
+    if (g < 1 || d < 1 || m < 0 || kfit < 1 || !(sigma > 0.0) || !L || !l || !p || !out)
+        return ORACLE_EINVAL;
+    if (kfit > g)
+        kfit = g;
+    int *nb = (int *)malloc(sizeof(int) * (size_t)kfit);
+    double *nd = (double *)malloc(sizeof(double) * (size_t)kfit);
+    if (!nb || !nd) {
+        free(nb); free(nd);
+        return ORACLE_ENOMEM;
+    }
+    for (int q = 0; q < m; ++q) {
+        double px = p[2 * q], py = p[2 * q + 1];
+        /* the kfit nearest in 2-D, by plain insertion */
+        for (int i = 0; i < kfit; ++i) {
+            nb[i] = -1;
+            nd[i] = INFINITY;
+        }
+        for (int j = 0; j < g; ++j) {
+            double dx = (double)l[2 * j] - px, dy = (double)l[2 * j + 1] - py;
+            double dj = dx * dx + dy * dy;
+            if (nb[kfit - 1] >= 0 && !before(dj, j, nd[kfit - 1], nb[kfit - 1]))
+                continue;
+            int pos = kfit - 1;
+            while (pos > 0 && (nb[pos - 1] < 0 || before(dj, j, nd[pos - 1], nb[pos - 1]))) {
+                nb[pos] = nb[pos - 1];
+                nd[pos] = nd[pos - 1];
+                --pos;
+            }
+            nb[pos] = j;
+            nd[pos] = dj;
+        }
+        /* weighted normal equations G a = r of the affine fit, z = (lx, ly, 1) */
+        double G[3][3] = {{0}}, W = 0.0;
+        for (int i = 0; i < kfit; ++i) {
+            double w = exp(-(nd[i] - nd[0]) / (2.0 * sigma * sigma));
+            double z[3] = {l[2 * nb[i]], l[2 * nb[i] + 1], 1.0};
+            for (int a = 0; a < 3; ++a)
+                for (int b = 0; b < 3; ++b)
+                    G[a][b] += w * z[a] * z[b];
+            W += w;
+        }
+        double det = G[0][0] * (G[1][1] * G[2][2] - G[1][2] * G[2][1]) -
+                     G[0][1] * (G[1][0] * G[2][2] - G[1][2] * G[2][0]) +
+                     G[0][2] * (G[1][0] * G[2][1] - G[1][1] * G[2][0]);
+        double md = (G[0][0] + G[1][1] + G[2][2]) / 3.0;
+        double *o = out + (size_t)q * d;
+        if (kfit >= 3 && det > 1e-12 * md * md * md) {
+            /* v = G^{-1} (px, py, 1) by Cramer's rule; the fitted map at p is
+             * sum_j w_j (v . z_j) L_j */
+            double e[3] = {px, py, 1.0}, v[3];
+            for (int c = 0; c < 3; ++c) {
+                double M[3][3];
+                for (int a = 0; a < 3; ++a)
+                    for (int b = 0; b < 3; ++b)
+                        M[a][b] = (b == c) ? e[a] : G[a][b];
+                v[c] = (M[0][0] * (M[1][1] * M[2][2] - M[1][2] * M[2][1]) -
+                        M[0][1] * (M[1][0] * M[2][2] - M[1][2] * M[2][0]) +
+                        M[0][2] * (M[1][0] * M[2][1] - M[1][1] * M[2][0])) / det;
+            }
+            for (int c = 0; c < d; ++c)
+                o[c] = 0.0;
+            for (int i = 0; i < kfit; ++i) {
+                double w = exp(-(nd[i] - nd[0]) / (2.0 * sigma * sigma));
+                double beta = w * (v[0] * l[2 * nb[i]] + v[1] * l[2 * nb[i] + 1] + v[2]);
+                for (int c = 0; c < d; ++c)
+                    o[c] += beta * (double)L[(size_t)nb[i] * d + c];
+            }
+        } else {
+            for (int c = 0; c < d; ++c)
+                o[c] = 0.0;
+            for (int i = 0; i < kfit; ++i) {
+                double w = exp(-(nd[i] - nd[0]) / (2.0 * sigma * sigma));
+                for (int c = 0; c < d; ++c)
+                    o[c] += w * (double)L[(size_t)nb[i] * d + c];
+            }
+            for (int c = 0; c < d; ++c)
+                o[c] /= W;
+        }
+    }
+    free(nb); free(nd);
+    return ORACLE_OK;
+}

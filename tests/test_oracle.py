@@ -520,3 +520,135 @@ def test_cutoff_weight_sensitivity_to_fp32_distances(oracle_mod, k, rows, expect
         assert worst > 1.0
     else:
         assert worst < 0.01
+
+
+# ---------------------------------------------------------------- online SOM training
+
+
+def _som_problem(seed, n=2000, d=5, side=6):
+    rng = np.random.default_rng(seed)
+    X = rng.normal(size=(n, d)).astype(np.float32) * 2
+    g = side * side
+    L = rng.normal(size=(g, d)).astype(np.float32)
+    j = np.arange(g)
+    l = np.stack([j % side, j // side], 1).astype(np.float32)
+    return rng, X, L, l
+
+
+def _kohonen_serial(X, L, l, rows, sigma, alpha):
+    """Textbook online SOM: one point per step, every landmark moves towards it by
+    alpha h(j, b) (x - L_j); the landmarks are kept in float32 between steps."""
+    L = L.astype(np.float32).copy()
+    l64 = l.astype(np.float64)
+    for t, r in enumerate(rows):
+        x = X[r].astype(np.float64)
+        L64 = L.astype(np.float64)
+        b = int(np.argmin(((x - L64) ** 2).sum(1)))
+        r2 = ((l64 - l64[b]) ** 2).sum(1)
+        h = (r2 == 0).astype(np.float64) if sigma[t] == 0 else np.exp(-r2 / (2 * sigma[t] ** 2))
+        L = (L64 + alpha[t] * h[:, None] * (x - L64)).astype(np.float32)
+    return L
+
+
+def test_som_train_batch_of_one_is_serial_online_rule(oracle_mod):
+    rng, X, L, l = _som_problem(31)
+    T = 60
+    rows = rng.integers(0, len(X), T)
+    sigma = 2.0 * (0.2 / 2.0) ** (np.arange(T) / (T - 1))      # 2 -> 0.2
+    alpha = 0.5 * (0.05 / 0.5) ** (np.arange(T) / (T - 1))     # 0.5 -> 0.05
+    sigma[17] = 0.0
+    got = oracle_mod.som_train(X, L, l, rows.reshape(T, 1), sigma, alpha)
+    expect = _kohonen_serial(X, L, l, rows, sigma, alpha)
+    np.testing.assert_allclose(got, expect, rtol=1e-6, atol=1e-6)
+    assert np.abs(got - L).max() > 0.1  # the landmarks moved
+
+
+def test_som_train_batch_step_is_average_of_single_point_updates(oracle_mod):
+    rng, X, L, l = _som_problem(32)
+    B = 64
+    rows = rng.integers(0, len(X), B)
+    rows[5] = -1            # presents no point, still counts in the batch size
+    rows[9] = len(X) + 3
+    sigma, alpha = np.array([1.3]), np.array([0.4])
+    got = oracle_mod.som_train(X, L, l, rows.reshape(1, B), sigma, alpha)
+    L64 = L.astype(np.float64)
+    l64 = l.astype(np.float64)
+    moves = np.zeros_like(L64)
+    for r in rows:
+        if r < 0 or r >= len(X):
+            continue
+        x = X[r].astype(np.float64)
+        b = int(np.argmin(((x - L64) ** 2).sum(1)))
+        h = np.exp(-((l64 - l64[b]) ** 2).sum(1) / (2 * 1.3 ** 2))
+        moves += 0.4 * h[:, None] * (x - L64)
+    np.testing.assert_allclose(got, (L64 + moves / B).astype(np.float32), rtol=1e-6, atol=1e-6)
+
+
+def test_som_train_frozen_and_zero_rate(oracle_mod):
+    rng, X, L, l = _som_problem(33)
+    T, B = 5, 50
+    rows = rng.integers(0, len(X), (T, B))
+    frozen = np.zeros(len(L), np.uint8)
+    frozen[[0, 7, 20]] = 1
+    got = oracle_mod.som_train(X, L, l, rows, np.full(T, 1.0), np.full(T, 0.3), frozen=frozen)
+    np.testing.assert_array_equal(got[[0, 7, 20]], L[[0, 7, 20]])
+    assert np.abs(got[1] - L[1]).max() > 0
+    same = oracle_mod.som_train(X, L, l, rows, np.full(T, 1.0), np.zeros(T))
+    np.testing.assert_array_equal(same, L)
+
+
+# ---------------------------------------------------------------- new-landmark fit
+
+
+def _fit_problem(seed, g=40, d=7):
+    rng = np.random.default_rng(seed)
+    l = rng.uniform(0, 8, (g, 2)).astype(np.float32)
+    return rng, l
+
+
+def test_fit_reproduces_affine_embedding(oracle_mod):
+    # landmarks on an affine image of the 2-D plane: the fit is exact there
+    rng, l = _fit_problem(41)
+    A = rng.normal(size=(7, 2))
+    c = rng.normal(size=7)
+    L = (l.astype(np.float64) @ A.T + c).astype(np.float32)
+    p = rng.uniform(1, 7, (25, 2)).astype(np.float32)
+    for kfit, sigma in ((3, 1.0), (8, 0.7), (40, 5.0)):
+        got = oracle_mod.fit_landmarks(L, l, p, kfit=kfit, sigma=sigma)
+        np.testing.assert_allclose(got, p.astype(np.float64) @ A.T + c, rtol=1e-4, atol=1e-4)
+
+
+def test_fit_matches_weighted_least_squares(oracle_mod):
+    rng, l = _fit_problem(42)
+    L = rng.normal(size=(len(l), 7)).astype(np.float32)
+    p = rng.uniform(0, 8, (20, 2)).astype(np.float32)
+    kfit, sigma = 9, 1.5
+    got = oracle_mod.fit_landmarks(L, l, p, kfit=kfit, sigma=sigma)
+    l64, L64 = l.astype(np.float64), L.astype(np.float64)
+    for q, pq in enumerate(p.astype(np.float64)):
+        d2 = ((l64 - pq) ** 2).sum(1)
+        nb = np.lexsort((np.arange(len(l)), d2))[:kfit]
+        w = np.exp(-d2[nb] / (2 * sigma ** 2))
+        Z = np.concatenate([l64[nb], np.ones((kfit, 1))], 1)
+        coef, *_ = np.linalg.lstsq(Z * np.sqrt(w)[:, None], L64[nb] * np.sqrt(w)[:, None], rcond=None)
+        np.testing.assert_allclose(got[q], np.append(pq, 1.0) @ coef, rtol=1e-9, atol=1e-9)
+
+
+def test_fit_interpolates_three_neighbours_and_collinear_falls_back(oracle_mod):
+    rng, l = _fit_problem(43)
+    L = rng.normal(size=(len(l), 7)).astype(np.float32)
+    # a new landmark placed on an existing one, fitted from three neighbours
+    # (non-collinear): the affine map through three points passes through them
+    got = oracle_mod.fit_landmarks(L, l, l[[4, 11]], kfit=3, sigma=1.0)
+    np.testing.assert_allclose(got, L[[4, 11]], rtol=1e-9, atol=1e-9)
+    # collinear 2-D neighbours determine no affine map: weighted mean
+    lc = np.stack([np.arange(6.0), np.zeros(6)], 1).astype(np.float32)
+    Lc = rng.normal(size=(6, 7)).astype(np.float32)
+    p = np.array([[2.3, 0.7]], np.float32)
+    got = oracle_mod.fit_landmarks(Lc, lc, p, kfit=6, sigma=2.0)
+    w = np.exp(-((lc.astype(np.float64) - p[0]) ** 2).sum(1) / 8.0)
+    np.testing.assert_allclose(got[0], np.average(Lc.astype(np.float64), axis=0, weights=w),
+                               rtol=1e-9, atol=1e-9)
+    # far from every landmark with a small sigma: still finite (no weight underflows)
+    far = oracle_mod.fit_landmarks(L, l, np.array([[500.0, -300.0]], np.float32), kfit=5, sigma=0.1)
+    assert np.all(np.isfinite(far))

@@ -163,6 +163,50 @@ int esom_landmark_update(esom_ctx *ctx, const float *X, int64_t n, int32_t d, in
                          float sigma, const int32_t *nearest, int64_t nearest_ld, int32_t *counts,
                          void *stream);
 
+/* Online SOM training (Section "Supervised training of self-organizing maps":
+ * the user's 2-D landmarks are the map topology, the high-dimensional
+ * landmarks are trained as its neuron weights, and the user sweeps the
+ * neighbourhood size sigma and learning rate alpha, pausing or fixing parts
+ * of the map at will).  Kohonen's online rule moves every landmark towards a
+ * presented point x by alpha h(j, b) (x - L_j), with b the point's nearest
+ * landmark (ties to the lower index) and h(j, b) = exp(-|l_j - l_b|^2 /
+ * (2 sigma^2)) (h = [j == b] for sigma = 0).  Step t presents the `batch`
+ * points X[batch_idx[t * batch + i]], finds their nearest landmarks against
+ * the step's landmarks, and applies the average of their single-point updates:
+ *   L_j += (alpha[t] / batch) sum_i h(j, b_i) (x_i - L_j)
+ * (batch = 1 is the serial online rule).  Landmarks with frozen[j] != 0 keep
+ * their position.  Batch entries outside [0, n) present no point but count
+ * in `batch`.  The sums run in FP64; L_hd is rounded to FP32 after each step.
+ *   X          device, n rows of d floats, row stride ldx
+ *   L_hd       device, g x d floats, trained in place (stream-ordered)
+ *   L_2d       device, g x 2 floats (the topology)
+ *   batch_idx  device, steps x batch int32 point indices (the caller draws them)
+ *   sigma, alpha  host, `steps` floats each: the schedule (sigma >= 0 finite,
+ *              alpha in [0, 1]); read during the call
+ *   frozen     device, g bytes, or NULL (none frozen)
+ * steps == 0 is a no-op.  Errors: ESOM_EINVAL for batch < 1, steps < 0, bad
+ * shapes (as esom_landmark_update), NULL arrays, schedule entries out of
+ * range; ESOM_ENOMEM for scratch beyond the context budget. */
+int esom_som_train(esom_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx, float *L_hd,
+                   const float *L_2d, int32_t g, const int32_t *batch_idx, int32_t batch,
+                   int32_t steps, const float *sigma, const float *alpha, const uint8_t *frozen,
+                   void *stream);
+
+/* High-dimensional positions of landmarks added to the map at 2-D positions
+ * p_2d (Section "Supervised training of self-organizing maps": the initial
+ * coordinates of a new landmark are fitted from the landmarks close to it in
+ * 2-D).  For each new position p: its min(kfit, g) nearest 2-D landmarks (ties
+ * to the lower index) get weights exp(-|l_j - p|^2 / (2 sigma^2)); an affine
+ * map from 2-D to the d-dimensional space is fitted to them by weighted least
+ * squares and evaluated at p (FP64).  When the neighbours determine no affine
+ * map (fewer than three, or collinear in 2-D), their weighted mean is used.
+ *   L_hd (g x d), L_2d (g x 2), p_2d (m x 2): device floats; L_new: device,
+ *   m x d floats (written).  No context: runs on the current device.
+ * Errors: ESOM_EINVAL for g, d out of range, m < 0, kfit outside [1, 64],
+ * sigma not finite and > 0, NULL or misaligned arrays (m > 0). */
+int esom_fit_landmarks(const float *L_hd, const float *L_2d, int32_t g, int32_t d, const float *p_2d,
+                       int32_t m, int32_t kfit, float sigma, float *L_new, void *stream);
+
 /* Waits for the work enqueued on `stream`; ESOM_EDEVICE reports a device fault. */
 int esom_sync(esom_ctx *ctx, void *stream);
 

@@ -17,7 +17,7 @@ namespace esom {
 
 template <int MODE, int DC, int KP>
 static hipError_t launch_dc(const EmbedArgs &a, int block, size_t smem, int num_cus, hipStream_t s) {
-    auto kern = embed_main<MODE, DC, KP>;
+    auto kern = a.lds_rows ? embed_main<MODE, DC, KP, 1> : embed_main<MODE, DC, KP, 0>;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, smem) != hipSuccess ||
         per_cu < 1)

@@ -292,11 +292,12 @@ __host__ __device__ inline size_t tile_lds_bytes(int mode, int ntiles, int dc) {
 }
 
 // Bytes of LDS one wave needs: candidate bitmaps (2 W words per lane), or for
-// KP > 16 the neighbour staging of the pair loop in the same space; then
-// thresholds, norms and the per-lane masks of non-empty bitmap words.
-__host__ __device__ inline int wave_smem_bytes(int kp, int npair_tiles) {
+// KP > 16 the neighbour staging of the pair loop (k entries of 10 bytes per
+// lane) in the same space; then thresholds, norms and the per-lane masks of
+// non-empty bitmap words.
+__host__ __device__ inline int wave_smem_bytes(int kp, int k, int npair_tiles) {
     const int bits = 2 * npair_tiles * 64 * 4;
-    const int nbr = kp > 16 ? kp * 64 * 10 : 0;
+    const int nbr = kp > 16 ? k * 64 * 10 : 0;
     return (bits > nbr ? bits : nbr) + 512 + 1024;
 }
 
@@ -586,9 +587,11 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
         // arithmetic cost more than it saved.)
 #pragma unroll
         for (int q = 0; q < KP; ++q) {
-            nbD2[q * 64 + lane] = d2q[q];
-            nbS[q * 64 + lane] = sq[q];
-            nbI[q * 64 + lane] = (unsigned short)jq[q];
+            if (q < a.k) {
+                nbD2[q * 64 + lane] = d2q[q];
+                nbS[q * 64 + lane] = sq[q];
+                nbI[q * 64 + lane] = (unsigned short)jq[q];
+            }
         }
         __builtin_amdgcn_fence(__ATOMIC_RELEASE, "wavefront");
         __builtin_amdgcn_wave_barrier();
@@ -714,7 +717,10 @@ __global__ void __launch_bounds__(256) embed_project(EmbedArgs a) {
     }
 }
 
-template <int MODE, int DC, int KP>
+// ROWS = 1: the block stages the padded landmark rows in LDS for the exact
+// rescoring (a.lds_rows); ROWS = 0: rows stream from memory.  The two are
+// separate instantiations so that each gets its own register allocation.
+template <int MODE, int DC, int KP, int ROWS>
 __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(EmbedArgs a) {
     extern __shared__ __align__(16) unsigned char smem[];
     constexpr int DP = 16 * DC;
@@ -732,7 +738,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
     unsigned short *permL = reinterpret_cast<unsigned short *>(smem + CENT_LDS_BYTES);
     unsigned short *iposL = permL + tab_bytes / 4;
     float *rowsL = reinterpret_cast<float *>(smem + CENT_LDS_BYTES + tab_bytes);
-    const size_t rows_bytes = a.lds_rows ? (((size_t)a.g * RS * 4 + 255) & ~(size_t)255) : 0;
+    const size_t rows_bytes = ROWS ? (((size_t)a.g * RS * 4 + 255) & ~(size_t)255) : 0;
     // optionally the screen operands (A tiles and norms), read by every wave
     // twice per 64 points
     const size_t a_bytes = tile_a_bytes(MODE, a.ntiles, DC);
@@ -744,7 +750,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         permL[e] = (unsigned short)a.perm[e];
         iposL[e] = (unsigned short)a.ipos[e];
     }
-    if (a.lds_rows) {
+    if constexpr (ROWS == 1) {
         for (int e = threadIdx.x; e < a.g * (DP / 4); e += blockDim.x) {
             const int j = e / (DP / 4), q = e % (DP / 4);
             reinterpret_cast<float4 *>(rowsL + (size_t)j * RS)[q] =
@@ -760,12 +766,12 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
     }
     __syncthreads();
     unsigned char *wsm = smem + CENT_LDS_BYTES + tab_bytes + rows_bytes + tiles_bytes +
-                         (size_t)wave * wave_smem_bytes(KP, W);
+                         (size_t)wave * wave_smem_bytes(KP, a.k, W);
     unsigned *bitsL = reinterpret_cast<unsigned *>(wsm);
     float *nbD2 = reinterpret_cast<float *>(wsm);
-    float *nbS = nbD2 + KP * 64;
-    unsigned short *nbI = reinterpret_cast<unsigned short *>(nbS + KP * 64);
-    const int nbr_bytes = KP > 16 ? KP * 64 * 10 : 0;
+    float *nbS = nbD2 + a.k * 64;
+    unsigned short *nbI = reinterpret_cast<unsigned short *>(nbS + a.k * 64);
+    const int nbr_bytes = KP > 16 ? a.k * 64 * 10 : 0;
     const int tail = (2 * W * 64 * 4 > nbr_bytes) ? 2 * W * 64 * 4 : nbr_bytes;
     float *certL = reinterpret_cast<float *>(wsm + tail);  // 64 certificate bounds (512 B reserved)
     unsigned long long *maskL = reinterpret_cast<unsigned long long *>(certL + 128);
@@ -1002,35 +1008,43 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         for (int q = 0; q < KP; ++q) sk[q] = INFINITY;
         double rej = INFINITY;
         int m = 0;
-        {
-            // Each lane walks its own candidates across all its words (one
-            // candidate per iteration), so the wave iterates max_l m_l times.
-            // The next non-empty word is read one word ahead.
+        // Each lane walks its own candidates across all its words (one candidate
+        // per iteration), so the wave iterates max_l m_l times.  The next
+        // non-empty word is read one word ahead.  The loop is wave-uniform (it
+        // ends when no lane has a candidate left); a lane without one rescores
+        // landmark 0 and inserts +inf, which leaves its list unchanged.  Keeping
+        // the insertion out of divergent control flow keeps the list in place
+        // in registers.
+        auto walk = [&](auto rows_in_lds) {
+            constexpr bool IN_LDS = decltype(rows_in_lds)::value;
             unsigned long long mk = valid ? maskL[lane] : 0ull;
             const unsigned long long *row = reinterpret_cast<const unsigned long long *>(bitsL) + h * W * 32 + i32;
-            int ntp = 0;
-            unsigned long long nb = 0ull;
+            int ntp = 0, ctp = 0;
+            unsigned long long nb = 0ull, b = 0ull;
             next_word(mk, row, nb, ntp);
-            unsigned long long b = 0ull;
-            int ctp = 0;
-            // The loop is wave-uniform (it ends when no lane has a candidate
-            // left); a lane without one rescores landmark 0 and inserts +inf,
-            // which leaves its list unchanged.  Keeping the insertion out of
-            // divergent control flow keeps the list in place in registers.
-            for (;;) {
+            // the lane's next candidate position (0 and act = false when none is left)
+            auto advance = [&](int &j, bool &act) {
                 if (b == 0ull && nb != 0ull) {
                     b = nb;
                     ctp = ntp;
                     next_word(mk, row, nb, ntp);
                 }
-                const bool act = b != 0ull;
-                if (__ballot(act) == 0ull) break;
-                const int bit = __builtin_ctzll(b);
+                act = b != 0ull;
+                const int bit = act ? __builtin_ctzll(b) : 0;
                 b &= b - 1ull;
                 // bit 32 h + pos of a word of tile pair ctp: position 64 ctp + 2 pos + h
-                const int j = act ? 64 * ctp + 2 * (bit & 31) + (bit >> 5) : 0;
+                j = act ? 64 * ctp + 2 * (bit & 31) + (bit >> 5) : 0;
+            };
+            int j;
+            bool act;
+            advance(j, act);
+            for (;;) {
+                if (__ballot(act) == 0ull) break;
+                int jn;
+                bool actn;
+                advance(jn, actn);
                 float acc = 0.f;
-                if (a.lds_rows) {
+                if constexpr (IN_LDS) {
                     const float4 *Lr = reinterpret_cast<const float4 *>(rowsL + row_offset<RS>(j));
 #pragma unroll
                     for (int q = 0; q < DP / 4; ++q) {
@@ -1058,8 +1072,11 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 // keys carry the landmark index (ties break on it), not the position
                 insert_sorted<KP>(sk, rej, act ? pack_key(acc, permL[j]) : (double)INFINITY);
                 m += act ? 1 : 0;
+                j = jn;
+                act = actn;
             }
-        }
+        };
+        walk(BoolTag<ROWS == 1>{});
         __builtin_amdgcn_wave_barrier();
 
         // k-th and (k+1)-th rescored distances
@@ -1079,11 +1096,12 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             // two rescored values are ordered correctly when their gap exceeds the sum
             // of their rounding bounds, (d_pad + 3) u each
             if (m > a.k && d2k1 - d2k <= 2.f * (DP + 3) * U32 * d2k1) reason |= R_NEARTIE;
-            // When the neighbour list itself is an output (its first entry is the
+            // When the caller asked for the neighbour list (its first entry is the
             // nearest landmark of the landmark update), adjacent entries closer
             // than the rounding bound go to the exact path too, so the list is
-            // ordered by exact distance.
-            if (a.knn_idx) {
+            // ordered by exact distance.  (The serving cache keeps the fast
+            // path's own order, which is what a fresh projection uses.)
+            if (a.knn_exact_order) {
                 float prev = key_d2(sk[0]);
 #pragma unroll
                 for (int q = 1; q < KP; ++q) {
@@ -1111,7 +1129,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 const float *xr = a.X + (valid ? pi : 0) * a.ldx;
                 auto d2x = [&](int jl) -> double {
                     const unsigned pos = iposL[jl];
-                    const float4 *Lr = a.lds_rows ? reinterpret_cast<const float4 *>(rowsL + row_offset<RS>(pos))
+                    const float4 *Lr = ROWS ? reinterpret_cast<const float4 *>(rowsL + row_offset<RS>(pos))
                                                   : reinterpret_cast<const float4 *>(a.Lpad + (size_t)pos * DP);
                     double acc = 0.0;
                     auto add4 = [&](float4 xv, float4 lv) {

@@ -29,6 +29,9 @@ struct esom_ctx {
     // landmark-update workspace
     void *uws = nullptr;
     size_t uws_bytes = 0;
+    // online SOM training: the gathered batch
+    float *som_xb = nullptr;
+    size_t som_xb_bytes = 0;
     int32_t *nearest = nullptr;
     int64_t nearest_cap = 0;
     // optional per-kernel timing: pending event quadruples (prep, main, exact, end)
@@ -167,7 +170,7 @@ Plan make_plan(int d, int g, int k, int mode, int candidates) {
     Plan p;
     p.dp = 16 * ((d + 15) / 16);
     p.dc = p.dp / 16;
-    p.kp = k <= 8 ? 8 : k <= 16 ? 16 : k <= 32 ? 32 : 0;
+    p.kp = k <= 8 ? 8 : k <= 16 ? 16 : k <= 24 ? 24 : k <= 32 ? 32 : 0;
     const int maxdc = mode == 1 ? FAST_MAX_DC_BF16 : FAST_MAX_DC_FP32;
     p.fast = p.kp != 0 && p.dc <= maxdc && g <= FAST_MAX_G;
     int C = candidates > 0 ? candidates : (mode == 1 ? 2 * k : k + 2);
@@ -194,7 +197,8 @@ bool embed_needs_pairs(int d, int g, const esom_params &P, int what) {
 int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t lds_per_block,
                   const float *X, int64_t n, int d, int64_t ldx, const float *L, const float *l2d,
                   int g, const esom_params &P, float *out, int32_t *knn_idx, float *knn_d2,
-                  int what, hipStream_t s, uint8_t *knn_mark, hipEvent_t *ev, int64_t chunk) {
+                  int what, hipStream_t s, uint8_t *knn_mark, hipEvent_t *ev, int64_t chunk,
+                  int exact_order) {
     const int knn_only = what == EMBED_KNN_ONLY;
     const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
     const bool need_pairs = embed_needs_pairs(d, g, P, what);
@@ -244,6 +248,7 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
     a.fb_thresh = sc.fb_thresh;
     a.counters = counters;
     a.knn_only = knn_only;
+    a.knn_exact_order = (exact_order && knn_idx) ? 1 : 0;
     // Points go in chunks of at most `chunk` (the fallback list's capacity):
     // each chunk is screened, then its listed points are recomputed, before
     // the next chunk reuses the list.
@@ -286,7 +291,7 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
 
 int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const float *L,
               const float *l2d, int g, const esom_params &P, float *out, int32_t *knn_idx,
-              float *knn_d2, int what, hipStream_t s, uint8_t *knn_mark) {
+              float *knn_d2, int what, hipStream_t s, uint8_t *knn_mark, int exact_order) {
     const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
     int st = ensure_scratch(c, n, g, pl.dp, embed_needs_pairs(d, g, P, what) ? g : 0, s);
     if (st != ESOM_OK) return st;
@@ -299,7 +304,7 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
         }
     }
     st = enqueue_embed(c->sc, c->counters, c->num_cus, c->lds_per_block, X, n, d, ldx, L, l2d, g, P,
-                       out, knn_idx, knn_d2, what, s, knn_mark, timed ? ev : nullptr, n);
+                       out, knn_idx, knn_d2, what, s, knn_mark, timed ? ev : nullptr, n, exact_order);
     if (timed) {
         if (st == ESOM_OK) {
             for (int i = 0; i < 4; ++i) c->pending.push_back(ev[i]);
@@ -454,6 +459,7 @@ void esom_destroy(esom_ctx *c) {
     c->pending.clear();
     dev_free(c, c->arena, c->arena_bytes);
     dev_free(c, c->uws, c->uws_bytes);
+    dev_free(c, reinterpret_cast<void *&>(c->som_xb), c->som_xb_bytes);
     dev_free(c, reinterpret_cast<void *&>(c->nearest), sizeof(int32_t) * (size_t)c->nearest_cap);
     dev_free(c, reinterpret_cast<void *&>(c->counters), sizeof(unsigned long long) * C_COUNT);
     delete c;
@@ -473,7 +479,128 @@ int esom_embed(esom_ctx *c, const float *X, int64_t n, int32_t d, int64_t ldx, c
     hipError_t e = hipSetDevice(c->device);
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     return run_embed(c, X, n, d, ldx, L_hd, L_2d, g, P, out, knn_idx, knn_dist2, EMBED_FULL,
-                     static_cast<hipStream_t>(stream));
+                     static_cast<hipStream_t>(stream), nullptr, 1);
+}
+
+namespace {
+
+int grow_nearest(esom_ctx *c, int64_t n, hipStream_t s) {
+    if (n <= c->nearest_cap) return ESOM_OK;
+    if (c->nearest) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        dev_free(c, reinterpret_cast<void *&>(c->nearest), sizeof(int32_t) * (size_t)c->nearest_cap);
+    }
+    int st = dev_alloc(c, reinterpret_cast<void **>(&c->nearest), sizeof(int32_t) * (size_t)n);
+    c->nearest_cap = st == ESOM_OK ? n : 0;
+    return st;
+}
+
+int grow_update_ws(esom_ctx *c, int64_t n, int g, int d, hipStream_t s) {
+    const size_t need = update_workspace_bytes(n, g, d);
+    if (need <= c->uws_bytes) return ESOM_OK;
+    if (c->uws) {
+        hipError_t e = hipStreamSynchronize(s);
+        if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+        dev_free(c, c->uws, c->uws_bytes);
+        c->uws_bytes = 0;
+    }
+    int st = dev_alloc(c, &c->uws, need);
+    if (st == ESOM_OK) c->uws_bytes = need;
+    return st;
+}
+
+}  // namespace
+
+int esom_som_train(esom_ctx *c, const float *X, int64_t n, int32_t d, int64_t ldx, float *L_hd,
+                   const float *L_2d, int32_t g, const int32_t *batch_idx, int32_t batch,
+                   int32_t steps, const float *sigma, const float *alpha, const uint8_t *frozen,
+                   void *stream) {
+    t_err.clear();
+    if (!c) return fail(ESOM_EINVAL, "ctx is NULL");
+    if (steps < 0) return fail(ESOM_EINVAL, "steps = %d < 0", steps);
+    if (batch < 1) return fail(ESOM_EINVAL, "batch = %d < 1", batch);
+    int st = validate_common(X, n, d, ldx, L_hd, g);
+    if (st != ESOM_OK) return st;
+    if (!L_2d || !aligned4(L_2d)) return fail(ESOM_EINVAL, "L_2d is NULL or not 4-byte aligned");
+    if (!batch_idx || !aligned4(batch_idx)) return fail(ESOM_EINVAL, "batch_idx is NULL or not 4-byte aligned");
+    if (steps > 0 && (!sigma || !alpha)) return fail(ESOM_EINVAL, "sigma and alpha are required");
+    for (int t = 0; t < steps; ++t) {
+        if (!(sigma[t] >= 0.f) || !isfinite(sigma[t]))
+            return fail(ESOM_EINVAL, "sigma[%d] = %g must be finite and >= 0", t, (double)sigma[t]);
+        if (!(alpha[t] >= 0.f && alpha[t] <= 1.f))
+            return fail(ESOM_EINVAL, "alpha[%d] = %g outside [0, 1]", t, (double)alpha[t]);
+    }
+    if (steps == 0) return ESOM_OK;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t xb = sizeof(float) * (size_t)batch * d;
+    if (xb > c->som_xb_bytes) {
+        if (c->som_xb) {
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            dev_free(c, reinterpret_cast<void *&>(c->som_xb), c->som_xb_bytes);
+            c->som_xb_bytes = 0;
+        }
+        st = dev_alloc(c, reinterpret_cast<void **>(&c->som_xb), xb);
+        if (st != ESOM_OK) return st;
+        c->som_xb_bytes = xb;
+    }
+    if ((st = grow_nearest(c, batch, s)) != ESOM_OK) return st;
+    if ((st = grow_update_ws(c, batch, g, d, s)) != ESOM_OK) return st;
+    esom_params P;
+    esom_default_params(&P);
+    P.k = 1;
+    P.mode = ESOM_MODE_FP32;
+    for (int t = 0; t < steps; ++t) {
+        const int32_t *rows = batch_idx + (size_t)t * batch;
+        e = launch_som_gather(X, n, ldx, d, rows, batch, c->som_xb, s);
+        if (e != hipSuccess) return hip_fail(e, "batch gather launch");
+        // best-matching landmarks of the batch against this step's landmarks
+        st = run_embed(c, c->som_xb, batch, d, d, L_hd, L_2d, g, P, nullptr, c->nearest, nullptr,
+                       EMBED_KNN_ONLY, s);
+        if (st != ESOM_OK) return st;
+        e = launch_som_mask(rows, batch, n, c->nearest, s);
+        if (e != hipSuccess) return hip_fail(e, "batch mask launch");
+        UpdateArgs u;
+        u.X = c->som_xb;
+        u.n = batch;
+        u.ldx = d;
+        u.d = d;
+        u.g = g;
+        u.kind = 2;
+        u.alpha = alpha[t];
+        u.sigma = sigma[t];
+        u.L = L_hd;
+        u.l2d = L_2d;
+        u.nearest = c->nearest;
+        u.nearest_ld = 1;
+        u.counts = nullptr;
+        u.frozen = frozen;
+        u.batch = batch;
+        e = launch_update(u, c->uws, c->num_cus, s);
+        if (e != hipSuccess) return hip_fail(e, "online SOM update launch");
+    }
+    return ESOM_OK;
+}
+
+int esom_fit_landmarks(const float *L_hd, const float *L_2d, int32_t g, int32_t d, const float *p_2d,
+                       int32_t m, int32_t kfit, float sigma, float *L_new, void *stream) {
+    t_err.clear();
+    if (g < 1 || g > ESOM_MAX_G) return fail(ESOM_EINVAL, "g = %d outside [1, %d]", g, ESOM_MAX_G);
+    if (d < 1 || d > ESOM_MAX_D) return fail(ESOM_EINVAL, "d = %d outside [1, %d]", d, ESOM_MAX_D);
+    if (m < 0) return fail(ESOM_EINVAL, "m = %d < 0", m);
+    if (kfit < 1 || kfit > 64) return fail(ESOM_EINVAL, "kfit = %d outside [1, 64]", kfit);
+    if (!(sigma > 0.f) || !isfinite(sigma)) return fail(ESOM_EINVAL, "sigma = %g must be finite and > 0", (double)sigma);
+    if (m == 0) return ESOM_OK;
+    if (!L_hd || !L_2d || !p_2d || !L_new || !aligned4(L_hd) || !aligned4(L_2d) || !aligned4(p_2d) ||
+        !aligned4(L_new))
+        return fail(ESOM_EINVAL, "NULL or misaligned array");
+    hipError_t e = launch_fit_landmarks(L_hd, L_2d, g, d, p_2d, m, kfit < g ? kfit : g, sigma, L_new,
+                                        static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "landmark fit launch");
+    return ESOM_OK;
 }
 
 int esom_landmark_update(esom_ctx *c, const float *X, int64_t n, int32_t d, int64_t ldx,

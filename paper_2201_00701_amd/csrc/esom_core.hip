@@ -772,6 +772,8 @@ hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s
         hipLaunchKernelGGL(embed_project<8>, dim3((unsigned)blocks), dim3(block), smem, s, a);
     else if (kp == 16)
         hipLaunchKernelGGL(embed_project<16>, dim3((unsigned)blocks), dim3(block), smem, s, a);
+    else if (kp == 24)
+        hipLaunchKernelGGL(embed_project<24>, dim3((unsigned)blocks), dim3(block), smem, s, a);
     else
         hipLaunchKernelGGL(embed_project<32>, dim3((unsigned)blocks), dim3(block), smem, s, a);
     return hipGetLastError();
@@ -784,16 +786,18 @@ hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s
 // that kernel, and launches it.
 hipError_t launch_main_m0_kp8(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m0_kp16(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m0_kp24(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m0_kp32(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m1_kp8(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m1_kp16(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m1_kp24(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m1_kp32(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 
 hipError_t launch_embed(const EmbedArgs &a0, int mode, int kp, int num_cus, size_t lds_per_block,
                         hipStream_t s) {
     EmbedArgs a = a0;
     const int dc = a.dp / 16;
-    const size_t wsm = (size_t)wave_smem_bytes(kp, a.npair_tiles);
+    const size_t wsm = (size_t)wave_smem_bytes(kp, a.k, a.npair_tiles);
     const size_t rows = ((size_t)a.g * (a.dp + 4) * 4 + 255) & ~(size_t)255;
     // Stage the landmark rows in LDS when a full block of waves (one block per
     // CU: 3 waves per SIMD in BF16 mode, 2 in FP32 mode) still fits beside
@@ -821,10 +825,12 @@ hipError_t launch_embed(const EmbedArgs &a0, int mode, int kp, int num_cus, size
     if (mode == 0) {
         if (kp == 8) return launch_main_m0_kp8(a, dc, block, smem, num_cus, s);
         if (kp == 16) return launch_main_m0_kp16(a, dc, block, smem, num_cus, s);
+        if (kp == 24) return launch_main_m0_kp24(a, dc, block, smem, num_cus, s);
         return launch_main_m0_kp32(a, dc, block, smem, num_cus, s);
     }
     if (kp == 8) return launch_main_m1_kp8(a, dc, block, smem, num_cus, s);
     if (kp == 16) return launch_main_m1_kp16(a, dc, block, smem, num_cus, s);
+    if (kp == 24) return launch_main_m1_kp24(a, dc, block, smem, num_cus, s);
     return launch_main_m1_kp32(a, dc, block, smem, num_cus, s);
 }
 

@@ -98,6 +98,9 @@ struct EmbedArgs {
     // (uncertified or near tie); a projection from cached neighbours sends
     // such points to the exact path again.
     uint8_t *knn_mark;
+    // 1: adjacent neighbours FP32 cannot order go to the exact path, so that
+    // knn_idx is sorted by exact distance (public calls that return the list)
+    int knn_exact_order;
 };
 
 // Launchers (esom_core.hip).
@@ -122,15 +125,25 @@ struct UpdateArgs {
     const int32_t *nearest;
     int64_t nearest_ld;  // element stride of nearest
     int32_t *counts;
+    const uint8_t *frozen = nullptr;  // kind 2: landmarks that keep their position
+    int64_t batch = 1;                // kind 2: batch size of the averaged online step
 };
 size_t update_workspace_bytes(int64_t n, int g, int d);
 hipError_t launch_update(const UpdateArgs &u, void *ws, int num_cus, hipStream_t s);
+
+// Online SOM training and the fit of added landmarks (esom_som.hip).
+hipError_t launch_som_gather(const float *X, int64_t n, int64_t ldx, int d, const int32_t *rows, int B,
+                             float *Xb, hipStream_t s);
+hipError_t launch_som_mask(const int32_t *rows, int B, int64_t n, int32_t *nearest, hipStream_t s);
+hipError_t launch_fit_landmarks(const float *L, const float *l2d, int g, int d, const float *p, int m,
+                                int kfit, float sigma, float *out, hipStream_t s);
 
 // Context-level helpers shared with the serving runtime (esom_api.cpp).
 enum EmbedWhat { EMBED_FULL = 0, EMBED_KNN_ONLY = 1, EMBED_PROJECT = 2 };
 int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const float *L,
               const float *l2d, int g, const esom_params &P, float *out, int32_t *knn_idx,
-              float *knn_d2, int what, hipStream_t s, uint8_t *knn_mark = nullptr);
+              float *knn_d2, int what, hipStream_t s, uint8_t *knn_mark = nullptr,
+              int exact_order = 0);
 // The launch sequence of one embed on the given scratch (laid out by carve for
 // at least min(n, chunk) points) and counters: landmark preparation, then per
 // chunk of at most `chunk` points (chunk <= 0: all) the fast kernel and the
@@ -138,7 +151,8 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
 int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t lds_per_block,
                   const float *X, int64_t n, int d, int64_t ldx, const float *L, const float *l2d,
                   int g, const esom_params &P, float *out, int32_t *knn_idx, float *knn_d2,
-                  int what, hipStream_t s, uint8_t *knn_mark, hipEvent_t *ev, int64_t chunk);
+                  int what, hipStream_t s, uint8_t *knn_mark, hipEvent_t *ev, int64_t chunk,
+                  int exact_order);
 // Whether an embed of this shape reads the g x g pair table.
 bool embed_needs_pairs(int d, int g, const esom_params &P, int what);
 // Lays out an embed scratch at base (NULL: only sizes it) for n points, g

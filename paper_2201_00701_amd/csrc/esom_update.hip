@@ -133,12 +133,19 @@ __global__ void upd_chunks(const int *__restrict__ counts, int g, int *__restric
     *nchunks_out = c;
 }
 
-// Blend: one block per landmark j, threads over dimensions.
+// Blend: one block per landmark j, threads over dimensions.  kind 0: k-means;
+// kind 1: batch SOM; kind 2: one online SOM step over a batch of `batch`
+// points, the average of the single-point online updates
+//   L_j += (alpha / batch) sum_b h_jb (S_b - c_b L_j),
+// skipping landmarks with frozen[j] != 0.
 __global__ void upd_finalize(const double *__restrict__ sums, const float *__restrict__ l2d, int g,
                              int d, int kind, float alpha, float sigma, float *__restrict__ L,
-                             const int *__restrict__ counts, int32_t *__restrict__ counts_out) {
+                             const int *__restrict__ counts, int32_t *__restrict__ counts_out,
+                             const uint8_t *__restrict__ frozen, int64_t batch) {
     const int j = blockIdx.x;
     if (j >= g) return;
+    if (counts_out && threadIdx.x == 0) counts_out[j] = counts[j];
+    if (kind == 2 && frozen && frozen[j]) return;
     double den = 0.0;
     const double s2 = 2.0 * (double)sigma * (double)sigma;
     if (kind == 0) {
@@ -173,12 +180,12 @@ __global__ void upd_finalize(const double *__restrict__ sums, const float *__res
                 num += hjb * sums[(size_t)b * (d + 1) + t];
             }
         }
-        if (den > 0.0) {
-            const double Lj = (double)L[(size_t)j * d + t];
+        const double Lj = (double)L[(size_t)j * d + t];
+        if (kind == 2)
+            L[(size_t)j * d + t] = (float)(Lj + (double)alpha / (double)batch * (num - den * Lj));
+        else if (den > 0.0)
             L[(size_t)j * d + t] = (float)(Lj + (double)alpha * (num / den - Lj));
-        }
     }
-    if (counts_out && threadIdx.x == 0) counts_out[j] = counts[j];
 }
 
 __global__ void upd_zero(double *__restrict__ sums, size_t ns, int *__restrict__ counts, int g) {
@@ -239,7 +246,8 @@ hipError_t launch_update(const UpdateArgs &u, void *ws, int num_cus, hipStream_t
                            u.d, perm, offsets, chunk_landmark, chunk_start, nchunks, sums);
     }
     hipLaunchKernelGGL(upd_finalize, dim3(u.g), dim3(u.d < 256 ? 64 * ((u.d + 63) / 64) : 256), 0, s,
-                       sums, u.l2d, u.g, u.d, u.kind, u.alpha, u.sigma, u.L, counts, u.counts);
+                       sums, u.l2d, u.g, u.d, u.kind, u.alpha, u.sigma, u.L, counts, u.counts,
+                       u.frozen, u.batch);
     return hipGetLastError();
 }
 

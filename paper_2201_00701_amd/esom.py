@@ -100,6 +100,11 @@ def load(path: str = LIB_PATH):
     lib.esom_landmark_update.argtypes = [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32, _f32,
                                          _f32, _vp, _i64, _vp, _vp]
     lib.esom_landmark_update.restype = ctypes.c_int
+    lib.esom_som_train.argtypes = [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _vp, _i32, _i32,
+                                   ctypes.POINTER(_f32), ctypes.POINTER(_f32), _vp, _vp]
+    lib.esom_som_train.restype = ctypes.c_int
+    lib.esom_fit_landmarks.argtypes = [_vp, _vp, _i32, _i32, _vp, _i32, _i32, _f32, _vp, _vp]
+    lib.esom_fit_landmarks.restype = ctypes.c_int
     lib.esom_sync.argtypes = [_vp, _vp]
     lib.esom_sync.restype = ctypes.c_int
     lib.esom_get_stats.argtypes = [_vp, _vp, ctypes.POINTER(esom_stats), _i32]
@@ -176,6 +181,19 @@ def esom_landmark_update(ctx, X, n, d, ldx, L_hd, L_2d, g, kind, alpha, sigma, n
     return load().esom_landmark_update(ctx, X, n, d, ldx, L_hd, L_2d or None, g, kind, alpha,
                                        sigma, nearest or None, nearest_ld, counts or None,
                                        stream or None)
+
+
+def esom_som_train(ctx, X, n, d, ldx, L_hd, L_2d, g, batch_idx, batch, steps, sigma, alpha,
+                   frozen=0, stream=0) -> int:
+    """sigma, alpha: host sequences of `steps` floats."""
+    sg = (_f32 * max(steps, 1))(*[float(v) for v in sigma])
+    al = (_f32 * max(steps, 1))(*[float(v) for v in alpha])
+    return load().esom_som_train(ctx, X, n, d, ldx, L_hd, L_2d, g, batch_idx, batch, steps, sg, al,
+                                 frozen or None, stream or None)
+
+
+def esom_fit_landmarks(L_hd, L_2d, g, d, p_2d, m, kfit, sigma, L_new, stream=0) -> int:
+    return load().esom_fit_landmarks(L_hd, L_2d, g, d, p_2d, m, kfit, sigma, L_new, stream or None)
 
 
 def esom_sync(ctx, stream=0) -> int:
@@ -283,6 +301,30 @@ class Context:
                                     cnt.data_ptr() if counts else 0, self._stream(stream)))
         return cnt
 
+    def som_train(self, X, L, l, batch_idx, sigma, alpha, frozen=None, stream=None):
+        """Online SOM steps (see esom_som_train): trains L in place.  batch_idx is a
+        steps x batch int32 device tensor; sigma and alpha are host sequences."""
+        import torch
+        X = _dev_f32(X, "X")
+        L = _dev_f32(L, "L", X.shape[1])
+        if not L.is_contiguous():
+            raise ValueError("L must be contiguous (it is trained in place)")
+        l = _dev_f32(l, "l", 2).contiguous()
+        if (batch_idx.dtype != torch.int32 or batch_idx.dim() != 2 or not batch_idx.is_contiguous()
+                or not batch_idx.is_cuda):
+            raise TypeError("batch_idx must be a contiguous steps x batch int32 device tensor")
+        steps, batch = batch_idx.shape
+        if len(sigma) != steps or len(alpha) != steps:
+            raise ValueError("sigma and alpha need one entry per step")
+        fz = 0
+        if frozen is not None:
+            if frozen.dtype != torch.uint8 or frozen.numel() != L.shape[0] or not frozen.is_contiguous():
+                raise TypeError("frozen must be a contiguous uint8 tensor of g entries")
+            fz = frozen.data_ptr()
+        _check(esom_som_train(self.handle, X.data_ptr(), X.shape[0], X.shape[1], X.stride(0),
+                              L.data_ptr(), l.data_ptr(), L.shape[0], batch_idx.data_ptr(), batch,
+                              steps, sigma, alpha, fz, self._stream(stream)))
+
     def set_timing(self, enable=True):
         _check(esom_set_timing(self.handle, enable))
 
@@ -303,6 +345,20 @@ class Context:
                                    rsn.ctypes.data, n)
         _check(rc)
         return pts[:min(n, n2)], rsn[:min(n, n2)]
+
+
+def fit_landmarks(L, l, p, kfit=8, sigma=1.0, stream=None):
+    """High-dimensional positions (m x d device tensor) of landmarks added at the
+    2-D positions p (m x 2 device tensor); see esom_fit_landmarks."""
+    import torch
+    L = _dev_f32(L, "L").contiguous()
+    l = _dev_f32(l, "l", 2).contiguous()
+    p = _dev_f32(p, "p", 2).contiguous()
+    out = torch.empty((p.shape[0], L.shape[1]), dtype=torch.float32, device=L.device)
+    st = Context._stream(stream)
+    _check(esom_fit_landmarks(L.data_ptr(), l.data_ptr(), L.shape[0], L.shape[1], p.data_ptr(),
+                              p.shape[0], kfit, sigma, out.data_ptr(), st))
+    return out
 
 
 # ---- serving (host arrays) ----------------------------------------------------------

@@ -1,0 +1,166 @@
+"""GPU parity of the online SOM training and of the fit of added landmarks
+(through the C ABI) against the FP64 oracle.  Training keeps the landmarks in
+FP32 between steps on both sides, so their results agree to FP32 rounding of
+differently ordered FP64 sums; the fit is FP64 on both sides, rounded to FP32
+on the GPU."""
+import sys
+
+import numpy as np
+import pytest
+
+pytestmark = pytest.mark.gpu
+
+
+def _say(msg):
+    print(msg, flush=True)
+    sys.stdout.flush()
+
+
+@pytest.fixture(scope="module")
+def torch_dev():
+    import torch
+    assert torch.cuda.is_available(), "GPU tests need a HIP device"
+    return torch
+
+
+@pytest.fixture(scope="module")
+def ctx(torch_dev):
+    from paper_2201_00701_amd.esom import Context
+    c = Context(0)
+    yield c
+    c.close()
+
+
+def _dev(torch, a):
+    return torch.from_numpy(np.ascontiguousarray(a)).cuda()
+
+
+def _schedule(T, s0, s1, a0, a1):
+    t = np.arange(T) / max(T - 1, 1)
+    return s0 * (s1 / s0) ** t, a0 * (a1 / a0) ** t
+
+
+def _train_case(torch, ctx, oracle_mod, X, L, l, rows, sigma, alpha, frozen=None, label=""):
+    Ld = _dev(torch, L)
+    fz = _dev(torch, frozen) if frozen is not None else None
+    ctx.som_train(_dev(torch, X), Ld, _dev(torch, l), _dev(torch, rows.astype(np.int32)),
+                  list(sigma), list(alpha), frozen=fz)
+    torch.cuda.synchronize()
+    got = Ld.cpu().numpy()
+    ref = oracle_mod.som_train(X, L, l, rows, np.asarray(sigma, np.float32).astype(np.float64),
+                               np.asarray(alpha, np.float32).astype(np.float64), frozen=frozen)
+    err = np.abs(got.astype(np.float64) - ref).max()
+    _say("%s: max |gpu - oracle| = %.3g, landmarks moved up to %.3g"
+         % (label, err, np.abs(ref - L).max()))
+    return got, ref
+
+
+def test_som_train_schedule_parity(torch_dev, ctx, oracle_mod):
+    from paper_2201_00701_amd import synth
+    w = synth.make("c2_fp32_1m", n=60_000)
+    rng = np.random.default_rng(5)
+    T, B = 12, 2048
+    rows = rng.integers(0, len(w.X), (T, B)).astype(np.int32)
+    rows[3, :7] = -1                      # entries that present no point
+    rows[4, 100] = len(w.X) + 5
+    sigma, alpha = _schedule(T, 3.0, 0.4, 0.5, 0.05)
+    sigma[6] = 0.0
+    frozen = np.zeros(len(w.L), np.uint8)
+    frozen[rng.choice(len(w.L), 20, replace=False)] = 1
+    _say("case som train n=%d d=%d g=%d T=%d B=%d" % (len(w.X), w.X.shape[1], len(w.L), T, B))
+    got, ref = _train_case(torch_dev, ctx, oracle_mod, w.X, w.L, w.l, rows, sigma, alpha, frozen,
+                           "som schedule")
+    np.testing.assert_allclose(got, ref, rtol=2e-5, atol=2e-5)
+    np.testing.assert_array_equal(got[frozen == 1], w.L[frozen == 1])
+
+
+def test_som_train_serial_steps_and_slow_shapes(torch_dev, ctx, oracle_mod):
+    from paper_2201_00701_amd import synth
+    rng = np.random.default_rng(6)
+    # batch size 1: the serial online rule
+    X = synth.mixture(5000, 12, 6, seed=61)
+    L = synth.landmarks_from_data(X, 64, seed=61)
+    l = synth.grid2d(64, 8)
+    T = 40
+    rows = rng.integers(0, len(X), (T, 1)).astype(np.int32)
+    sigma, alpha = _schedule(T, 2.0, 0.3, 0.6, 0.1)
+    _say("case som train batch 1, %d steps" % T)
+    got, ref = _train_case(torch_dev, ctx, oracle_mod, X, L, l, rows, sigma, alpha, None, "som serial")
+    np.testing.assert_allclose(got, ref, rtol=2e-5, atol=2e-5)
+    # more landmarks and dimensions than the fast kernels take: the nearest
+    # landmarks come from the exact path
+    X = synth.mixture(3000, 70, 6, seed=62)
+    L = synth.landmarks_from_data(X, 4200, seed=62)
+    l = synth.grid2d(4200, 70)
+    rows = rng.integers(0, len(X), (3, 256)).astype(np.int32)
+    _say("case som train d=70 g=4200 (exact-path nearest landmarks)")
+    got, ref = _train_case(torch_dev, ctx, oracle_mod, X, L, l, rows, [1.5, 0.8, 0.0], [0.3, 0.2, 0.1],
+                           None, "som slow shapes")
+    np.testing.assert_allclose(got, ref, rtol=2e-5, atol=2e-5)
+    # alpha = 0 leaves the landmarks exactly as they were
+    Ld = _dev(torch_dev, L)
+    ctx.som_train(_dev(torch_dev, X), Ld, _dev(torch_dev, l), _dev(torch_dev, rows), [1.0] * 3, [0.0] * 3)
+    torch_dev.cuda.synchronize()
+    np.testing.assert_array_equal(Ld.cpu().numpy(), L)
+
+
+def test_fit_landmarks_parity(torch_dev, oracle_mod):
+    from paper_2201_00701_amd import esom, synth
+    rng = np.random.default_rng(7)
+    X = synth.mixture(20_000, 32, 10, seed=71)
+    L = synth.landmarks_from_data(X, 400, seed=71)
+    l = synth.grid2d(400, 20) + rng.normal(0, 0.05, (400, 2)).astype(np.float32)
+    p = np.concatenate([rng.uniform(-1, 20, (60, 2)), l[[0, 37, 399]], [[300.0, -50.0]]]).astype(np.float32)
+    Ld, ld, pd = _dev(torch_dev, L), _dev(torch_dev, l), _dev(torch_dev, p)
+    for kfit, sigma in ((3, 1.0), (8, 0.7), (8, 3.0), (64, 2.0)):
+        _say("case fit landmarks kfit=%d sigma=%g m=%d" % (kfit, sigma, len(p)))
+        got = esom.fit_landmarks(Ld, ld, pd, kfit=kfit, sigma=sigma).cpu().numpy()
+        ref = oracle_mod.fit_landmarks(L, l, p, kfit=kfit, sigma=sigma)
+        scale = np.abs(ref).max(axis=1, keepdims=True) + 1.0
+        err = (np.abs(got - ref) / scale).max()
+        _say("  max relative error %.3g" % err)
+        assert err < 1e-5
+    # collinear 2-D landmarks: the weighted mean
+    lc = np.stack([np.arange(50.0), np.zeros(50)], 1).astype(np.float32)
+    Lc = L[:50].copy()
+    pc = np.array([[3.3, 1.0], [40.0, -2.0]], np.float32)
+    got = esom.fit_landmarks(_dev(torch_dev, Lc), _dev(torch_dev, lc), _dev(torch_dev, pc), kfit=6,
+                             sigma=2.0).cpu().numpy()
+    ref = oracle_mod.fit_landmarks(Lc, lc, pc, kfit=6, sigma=2.0)
+    np.testing.assert_allclose(got, ref, rtol=1e-5, atol=1e-5)
+
+
+def test_som_invalid_arguments(torch_dev, ctx):
+    from paper_2201_00701_amd import esom
+    X = torch_dev.zeros((100, 4), device="cuda")
+    L = torch_dev.zeros((10, 4), device="cuda")
+    l = torch_dev.zeros((10, 2), device="cuda")
+    rows = torch_dev.zeros((2, 5), dtype=torch_dev.int32, device="cuda")
+    _say("case som invalid arguments")
+
+    def train(batch=5, steps=2, sigma=(1.0, 1.0), alpha=(0.1, 0.1)):
+        return esom.esom_som_train(ctx.handle, X.data_ptr(), 100, 4, 4, L.data_ptr(), l.data_ptr(), 10,
+                                   rows.data_ptr(), batch, steps, sigma, alpha)
+
+    assert train() == esom.ESOM_OK
+    assert train(batch=0) == esom.ESOM_EINVAL
+    assert train(steps=-1, sigma=(), alpha=()) == esom.ESOM_EINVAL
+    assert train(sigma=(1.0, -1.0)) == esom.ESOM_EINVAL
+    assert train(alpha=(0.1, 1.5)) == esom.ESOM_EINVAL
+    assert train(sigma=(1.0, float("nan"))) == esom.ESOM_EINVAL
+    assert train(steps=0, sigma=(), alpha=()) == esom.ESOM_OK
+    out = torch_dev.zeros((3, 4), device="cuda")
+    p = torch_dev.zeros((3, 2), device="cuda")
+
+    def fit(kfit=3, sigma=1.0, g=10, d=4, m=3):
+        return esom.esom_fit_landmarks(L.data_ptr(), l.data_ptr(), g, d, p.data_ptr(), m, kfit, sigma,
+                                       out.data_ptr())
+
+    assert fit() == esom.ESOM_OK
+    assert fit(kfit=0) == esom.ESOM_EINVAL
+    assert fit(kfit=65) == esom.ESOM_EINVAL
+    assert fit(sigma=0.0) == esom.ESOM_EINVAL
+    assert fit(m=-1) == esom.ESOM_EINVAL
+    assert fit(d=0) == esom.ESOM_EINVAL
+    assert fit(kfit=64) == esom.ESOM_OK   # more than g: clamped to g
+    torch_dev.cuda.synchronize()

@@ -362,7 +362,8 @@ def serve_mix(n_requests=2000, warmup=200, rate=200.0, budget=8 << 30, slots=4, 
             "cache_hits": int(sum(infos[i]["cache_hit"] for i in range(warmup, total))),
             "graph_replays": int(sum(infos[i]["graph_replay"] for i in range(warmup, total))),
             "slots": slots, "budget_gib": budget / float(1 << 30), "peak_gib": st["peak_bytes"] / float(1 << 30),
-            "mode": "bf16"}
+            "admission_waits": int(st["admission_waits"]), "max_queued": int(st["max_queued"]),
+            "rejected": int(st["rejected"]), "failed": int(st["failed"]), "mode": "bf16"}
 
 
 def main():
@@ -378,6 +379,8 @@ def main():
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
     ap.add_argument("--serve-requests", type=int, default=2000)
+    ap.add_argument("--tight-budget-mib", type=int, default=384,
+                    help="HBM budget of the second serving run (admission binds)")
     ap.add_argument("--calibrate-copy", action="store_true",
                     help="also run a plain 256 MiB device copy (the reference kernel for "
                          "scaling HBM byte counters)")
@@ -457,9 +460,16 @@ def main():
     if not args.no_serve:
         print("bench: serving mix (%d requests)" % args.serve_requests, file=sys.stderr, flush=True)
         line["serving"] = serve_mix(n_requests=args.serve_requests)
-        print("bench: serving p50 %.2f ms p99 %.2f ms" % (line["serving"]["p50_ms"],
-                                                          line["serving"]["p99_ms"]),
+        print("bench: serving p50 %.2f ms p99 %.2f ms, %d graph replays" % (
+            line["serving"]["p50_ms"], line["serving"]["p99_ms"], line["serving"]["graph_replays"]),
               file=sys.stderr, flush=True)
+        # the same mix under a budget small enough that admission waits for memory
+        line["serving_tight_budget"] = serve_mix(n_requests=args.serve_requests,
+                                                 budget=args.tight_budget_mib << 20)
+        t = line["serving_tight_budget"]
+        print("bench: serving (%d MiB budget) p50 %.2f ms p99 %.2f ms, %d admission waits, "
+              "max queue %d" % (args.tight_budget_mib, t["p50_ms"], t["p99_ms"], t["admission_waits"],
+                                t["max_queued"]), file=sys.stderr, flush=True)
     print(json.dumps(line), flush=True)
 
 

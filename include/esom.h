@@ -245,8 +245,10 @@ int esom_set_timing(esom_ctx *ctx, int32_t enable);
  * exactly what esom_embed computes for the same inputs (results do not depend
  * on what else runs).  Resident datasets cache their last k-nearest result:
  * a request that changes only 2-D landmarks reuses it and skips the distance
- * screen.  Repeated identical frames on a slot are replayed from a captured
- * hipGraph.  All host pointers below are host memory; the server owns its
+ * screen.  A frame on a resident dataset that repeats on a slot (same
+ * dataset, shapes, parameters and cache use) is captured into a hipGraph the
+ * second time and replayed after that; requests on a resident dataset go to a
+ * free slot holding a graph of it when there is one.  All host pointers below are host memory; the server owns its
  * device and pinned staging memory.  Every submitted request must be waited
  * for (esom_serve_wait) to release its bookkeeping. */
 typedef struct esom_server esom_server;
@@ -266,6 +268,9 @@ typedef struct {
     int64_t completed, failed, rejected, points, cache_hits, graph_replays;
     int64_t queued, in_flight, slots;
     int64_t budget_bytes, resident_bytes, held_bytes, peak_bytes;
+    int64_t admission_waits; /* requests that waited at the head of the queue
+                                for device memory (the budget) */
+    int64_t max_queued;      /* deepest queue seen at submission */
     double now_ms;
 } esom_serve_stats;
 

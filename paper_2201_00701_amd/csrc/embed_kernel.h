@@ -274,6 +274,10 @@ template <bool B>
 struct BoolTag {
     static constexpr bool value = B;
 };
+template <int V>
+struct IntTag {
+    static constexpr int value = V;
+};
 
 // LDS bytes of the block-wide centroid copy (padded dimension <= 128).
 constexpr int CENT_LDS_BYTES = 512;
@@ -787,68 +791,74 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
     for (int64_t wt = (int64_t)wave * gridDim.x + blockIdx.x; wt < nwt; wt += (int64_t)gridDim.x * wpb) {
         const int64_t pbase = wt * 64;
 
-        // ---------------- point operands (centred), and |x - c|^2
-        PointOperand<MODE, DC> P;
-        float xnp[2], dxp[2];  // |x - c|^2 and, in BF16 mode, |bf16(x - c) - (x - c)|^2
+        // ---------------- point operands (centred), and |x - c|^2.  Pass 1
+        // always runs on the BF16 operand; FP32 mode builds its FP32 operand
+        // for pass 2 afterwards.
+        PointOperand<1, DC> P16;
+        float xnp[2], dxp[2];  // |x - c|^2 and |bf16(x - c) - (x - c)|^2
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             const int64_t pi = pbase + 32 * p + i32;
             const bool valid = pi < a.n;
             const float *xr = a.X + (valid ? pi : 0) * a.ldx;
             float part = 0.f, dpart = 0.f;
-            if constexpr (MODE == 1) {
 #pragma unroll
-                for (int c = 0; c < DC; ++c) {
-                    unsigned w[4];
-                    float4 xv[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
-                    if (a.x_vec4 && valid) {
-                        const float4 *x4 = reinterpret_cast<const float4 *>(xr + 16 * c + 8 * h);
-                        const float4 *c4 = reinterpret_cast<const float4 *>(centL + 16 * c + 8 * h);
+            for (int c = 0; c < DC; ++c) {
+                unsigned w[4];
+                float4 xv[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
+                if (a.x_vec4 && valid) {
+                    const float4 *x4 = reinterpret_cast<const float4 *>(xr + 16 * c + 8 * h);
+                    const float4 *c4 = reinterpret_cast<const float4 *>(centL + 16 * c + 8 * h);
 #pragma unroll
-                        for (int u = 0; u < 2; ++u) {
-                            const float4 q = x4[u], cv = c4[u];
-                            xv[u] = make_float4(q.x - cv.x, q.y - cv.y, q.z - cv.z, q.w - cv.w);
-                        }
+                    for (int u = 0; u < 2; ++u) {
+                        const float4 q = x4[u], cv = c4[u];
+                        xv[u] = make_float4(q.x - cv.x, q.y - cv.y, q.z - cv.z, q.w - cv.w);
                     }
+                }
 #pragma unroll
-                    for (int e = 0; e < 8; e += 2) {
-                        const int d0 = 16 * c + 8 * h + e;
-                        const float4 &xq = xv[e >> 2];
-                        float v0 = (e & 2) ? xq.z : xq.x, v1 = (e & 2) ? xq.w : xq.y;
-                        if (!a.x_vec4) {
-                            v0 = (valid && d0 < a.d) ? xr[d0] - centL[d0] : 0.f;
-                            v1 = (valid && d0 + 1 < a.d) ? xr[d0 + 1] - centL[d0 + 1] : 0.f;
-                        }
-                        part = fmaf(v0, v0, part);
-                        part = fmaf(v1, v1, part);
-                        const unsigned b0 = bf16_bits_rne(v0), b1 = bf16_bits_rne(v1);
-                        // quantisation errors (exact in FP32)
-                        const float q0 = __uint_as_float(b0 << 16) - v0, q1 = __uint_as_float(b1 << 16) - v1;
-                        dpart = fmaf(q0, q0, dpart);
-                        dpart = fmaf(q1, q1, dpart);
-                        w[e >> 1] = b0 | (b1 << 16);
+                for (int e = 0; e < 8; e += 2) {
+                    const int d0 = 16 * c + 8 * h + e;
+                    const float4 &xq = xv[e >> 2];
+                    float v0 = (e & 2) ? xq.z : xq.x, v1 = (e & 2) ? xq.w : xq.y;
+                    if (!a.x_vec4) {
+                        v0 = (valid && d0 < a.d) ? xr[d0] - centL[d0] : 0.f;
+                        v1 = (valid && d0 + 1 < a.d) ? xr[d0 + 1] - centL[d0 + 1] : 0.f;
                     }
-                    u32x4 wv = {w[0], w[1], w[2], w[3]};
-                    P.b[p][c] = __builtin_bit_cast(bf16x8, wv);
+                    part = fmaf(v0, v0, part);
+                    part = fmaf(v1, v1, part);
+                    const unsigned b0 = bf16_bits_rne(v0), b1 = bf16_bits_rne(v1);
+                    // quantisation errors (exact in FP32)
+                    const float q0 = __uint_as_float(b0 << 16) - v0, q1 = __uint_as_float(b1 << 16) - v1;
+                    dpart = fmaf(q0, q0, dpart);
+                    dpart = fmaf(q1, q1, dpart);
+                    w[e >> 1] = b0 | (b1 << 16);
                 }
-            } else {
-#pragma unroll
-                for (int s = 0; s < 8 * DC; ++s) {
-                    const int dd = 2 * s + h;
-                    const float v = (valid && dd < a.d) ? xr[dd] - centL[dd] : 0.f;
-                    part = fmaf(v, v, part);
-                    P.b[p][s] = v;
-                }
+                u32x4 wv = {w[0], w[1], w[2], w[3]};
+                P16.b[p][c] = __builtin_bit_cast(bf16x8, wv);
             }
             xnp[p] = part + __shfl_xor(part, 32);
-            dxp[p] = (MODE == 1) ? dpart + __shfl_xor(dpart, 32) : 0.f;
+            dxp[p] = dpart + __shfl_xor(dpart, 32);
+        }
+        // Rigorous bounds of the screen's rounding error in key units, per
+        // point.  With a = -2(L - c) and its BF16 image a + da, x' = x - c and
+        // its BF16 image x' + dx: |x'.da + dx.a + dx.da| <= |x'| max|da| + |dx|
+        // (max|a| + max|da|) (|dx| exact per point, max|da| from the
+        // preparation); plus FP32 accumulation and centring, (2 d_pad + 16) u
+        // (|x'| + max|L - c|)^2.  FP32 operands are exact and 2 (2u + u^2) |x'|
+        // max|L - c| bounds their products.  The FP32 evaluation of the bound
+        // is covered by the factor 1.01.
+        float e16[2], e32[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            const float sx = sqrtf(xnp[p]);
+            const float facc = (2.f * DP + 16.f) * U32 * (sx + lmax) * (sx + lmax);
+            e16[p] = 1.01f * (sx * qa + sqrtf(dxp[p]) * (2.f * lmax + qa) + facc);
+            e32[p] = 1.01f * (2.f * (2.f * U32 + U32 * U32) * sx * lmax + facc);
         }
 
-        // ---------------- pass 1: group minima of the keys.  BF16 mode adds
-        // |x - c|^2 once per group afterwards (rounding is monotone, so the
-        // minimum of the sums equals the sum with the minimum) and takes FP32
-        // minima; FP32 mode, where this measured slower, adds it per key and
-        // takes integer minima of the bit patterns of key + |x - c|^2.
+        // ---------------- pass 1: group minima of the BF16 keys; |x - c|^2 is
+        // added once per group afterwards (rounding is monotone, so the
+        // minimum of the sums equals the sum with the minimum).
         float gmin[2][2][16];
 #pragma unroll
         for (int p = 0; p < 2; ++p)
@@ -861,25 +871,22 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
 #pragma unroll
             for (int p = 0; p < 2; ++p)
 #pragma unroll
-                for (int r = 0; r < 16; ++r) {
-                    if constexpr (MODE == 1)
-                        gmin[p][half][r] = vmin32(gmin[p][half][r], acc[p][r], ninf);
-                    else
-                        gmin[p][half][r] = __int_as_float(
-                            min(__float_as_int(gmin[p][half][r]), __float_as_int(acc[p][r] + xnp[p])));
-                }
+                for (int r = 0; r < 16; ++r) gmin[p][half][r] = vmin32(gmin[p][half][r], acc[p][r], ninf);
         };
-        // one screen pass over all tiles, operands from LDS or global memory
-        auto screen_pass = [&](auto in_lds, auto consume, auto store) {
-            const void *Ab = decltype(in_lds)::value ? static_cast<const void *>(tilesL) : a.A;
+        // one screen pass over all tiles with the operand of precision OM,
+        // tiles from the block's LDS copy or from global memory
+        auto screen_pass = [&](auto in_lds, auto opm, const auto &Pop, const void *Aglob, auto consume,
+                               auto store) {
+            constexpr int OM = decltype(opm)::value;
+            const void *Ab = decltype(in_lds)::value ? static_cast<const void *>(tilesL) : Aglob;
             const float *Nb = decltype(in_lds)::value ? normsL : a.norms;
-            TileRegs<MODE, DC> T;
+            TileRegs<OM, DC> T;
             for (int tp = 0; tp < W; ++tp) {
 #pragma unroll
                 for (int half = 0; half < 2; ++half) {
                     f32x16 acc[2];
-                    load_tile<MODE, DC>(Ab, 2 * tp + half, lane, T);
-                    screen_tile<MODE, DC>(Nb, 2 * tp + half, lane, T, P, acc);
+                    load_tile<OM, DC>(Ab, 2 * tp + half, lane, T);
+                    screen_tile<OM, DC>(Nb, 2 * tp + half, lane, T, Pop, acc);
                     consume(acc, half);
                 }
                 store(tp);
@@ -887,16 +894,27 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         };
         {
             auto no_store = [](int) {};
-            if (a.lds_tiles)
-                screen_pass(BoolTag<true>{}, pass1_consume, no_store);
-            else
-                screen_pass(BoolTag<false>{}, pass1_consume, no_store);
+            if constexpr (MODE == 1) {
+                if (a.lds_tiles)
+                    screen_pass(BoolTag<true>{}, IntTag<1>{}, P16, a.A, pass1_consume, no_store);
+                else
+                    screen_pass(BoolTag<false>{}, IntTag<1>{}, P16, a.A, pass1_consume, no_store);
+            } else {
+                // FP32 mode: the BF16 tiles stream from global memory (the LDS
+                // copy holds the FP32 tiles of pass 2)
+                screen_pass(BoolTag<false>{}, IntTag<1>{}, P16, a.A16, pass1_consume, no_store);
+            }
         }
         // thresholds: a lane's jsel-th smallest group minimum (negative values,
         // from rounding, count as 0), as a key.  BF16 mode screens each half of
         // the landmarks against its own lane's value (each half then holds at
         // least jsel candidates, 2 jsel >= C in all) and certifies against the
-        // smaller of the two; FP32 mode (C close to k) uses the larger for both.
+        // smaller of the two.  FP32 mode (C close to k) takes the larger for
+        // both halves and screens the FP32 keys against it widened by both
+        // error bounds: a landmark counted by a BF16 group minimum has an
+        // exact key at most E16 above it and an FP32 key at most E32 above
+        // that, so each half again holds at least jsel candidates; the
+        // certificate uses the FP32 criterion itself.
         float tau[2], taucert[2];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
@@ -905,16 +923,37 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             for (int r = 0; r < 16; ++r) {
                 // approximate delta^2 as bit patterns; negative values (rounding)
                 // become 0, and integer order is then float order
-                v0[r] = max(__float_as_int(MODE == 1 ? gmin[p][0][r] + xnp[p] : gmin[p][0][r]), 0);
-                v1[r] = max(__float_as_int(MODE == 1 ? gmin[p][1][r] + xnp[p] : gmin[p][1][r]), 0);
+                v0[r] = max(__float_as_int(gmin[p][0][r] + xnp[p]), 0);
+                v1[r] = max(__float_as_int(gmin[p][1][r] + xnp[p]), 0);
             }
             int tl = select_jth(v0, v1, a.jsel);
             tl = min(tl, 0x7F7FFFFF);  // +inf (too few landmarks) -> FLT_MAX
             const float own = __int_as_float(tl), oth = __int_as_float(__shfl_xor(tl, 32));
-            const float tb = MODE == 1 ? own : fmaxf(own, oth);
-            const float tc = MODE == 1 ? fminf(own, oth) : fmaxf(own, oth);
-            tau[p] = (tb >= FLT_MAX) ? FLT_MAX : tb - xnp[p];
-            taucert[p] = (tc >= FLT_MAX) ? FLT_MAX : tc - xnp[p];
+            if constexpr (MODE == 1) {
+                tau[p] = (own >= FLT_MAX) ? FLT_MAX : own - xnp[p];
+                const float tc = fminf(own, oth);
+                taucert[p] = (tc >= FLT_MAX) ? FLT_MAX : tc - xnp[p];
+            } else {
+                const float tb = fmaxf(own, oth);
+                tau[p] = (tb >= FLT_MAX) ? FLT_MAX : (tb - xnp[p]) + (e16[p] + e32[p]);
+                taucert[p] = tau[p];
+            }
+        }
+
+        // FP32 mode: the FP32 operand of pass 2 (the rows are still in cache)
+        PointOperand<0, DC> P32;
+        if constexpr (MODE == 0) {
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int64_t pi = pbase + 32 * p + i32;
+                const bool valid = pi < a.n;
+                const float *xr = a.X + (valid ? pi : 0) * a.ldx;
+#pragma unroll
+                for (int s = 0; s < 8 * DC; ++s) {
+                    const int dd = 2 * s + h;
+                    P32.b[p][s] = (valid && dd < a.d) ? xr[dd] - centL[dd] : 0.f;
+                }
+            }
         }
 
         // ---------------- pass 2: candidate bitmaps (key <= tau) into LDS.  The
@@ -940,32 +979,25 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                     nonempty[p] |= (unsigned long long)(wd != 0u) << tp;
                 }
             };
-            if (a.lds_tiles)
-                screen_pass(BoolTag<true>{}, pass2_consume, pass2_store);
-            else
-                screen_pass(BoolTag<false>{}, pass2_consume, pass2_store);
+            if constexpr (MODE == 1) {
+                if (a.lds_tiles)
+                    screen_pass(BoolTag<true>{}, IntTag<1>{}, P16, a.A, pass2_consume, pass2_store);
+                else
+                    screen_pass(BoolTag<false>{}, IntTag<1>{}, P16, a.A, pass2_consume, pass2_store);
+            } else {
+                if (a.lds_tiles)
+                    screen_pass(BoolTag<true>{}, IntTag<0>{}, P32, a.A, pass2_consume, pass2_store);
+                else
+                    screen_pass(BoolTag<false>{}, IntTag<0>{}, P32, a.A, pass2_consume, pass2_store);
+            }
         }
-        // Certificate bound per point: a non-candidate's exact distance^2 exceeds
-        // tau + |x - c|^2 - E, E a rigorous bound of the screen's error.  With
-        // a = -2(L - c) and its BF16 image a + da, x' = x - c and its BF16 image
-        // x' + dx: |x'.da + dx.a + dx.da| <= |x'| max|da| + |dx| (max|a| + max|da|)
-        // (|dx| exact per point, max|da| from the preparation); plus FP32
-        // accumulation and centring, (2 d_pad + 16) u (|x'| + max|L - c|)^2.  In
-        // FP32 mode the operands are exact and 2 (2u + u^2) |x'| max|L - c| bounds
-        // the products.  The FP32 evaluation of the bound is covered by 1.01 and
-        // by 4u of the terms.
+        // Certificate bound per point: a non-candidate's exact distance^2
+        // exceeds tau + |x - c|^2 - E, with E the error bound of the keys pass 2
+        // compared (e16 in BF16 mode, e32 in FP32 mode).
         if (h == 0) {
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                const float sx = sqrtf(xnp[p]);
-                const float facc = (2.f * DP + 16.f) * U32 * (sx + lmax) * (sx + lmax);
-                float E;
-                if constexpr (MODE == 1) {
-                    const float dx = sqrtf(dxp[p]);
-                    E = 1.01f * (sx * qa + dx * (2.f * lmax + qa) + facc);
-                } else {
-                    E = 1.01f * (2.f * (2.f * U32 + U32 * U32) * sx * lmax + facc);
-                }
+                const float E = MODE == 1 ? e16[p] : e32[p];
                 const float tc = taucert[p];
                 float rhs = tc + xnp[p] - E;
                 rhs -= 4.f * U32 * (fabsf(tc) + xnp[p] + E);

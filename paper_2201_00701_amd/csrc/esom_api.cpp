@@ -97,6 +97,7 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg) {
     };
     sc.prep.cent = static_cast<float *>(take(sizeof(float) * dp));
     sc.prep.A = take(sizeof(float) * (size_t)ntiles * TILE * dp);
+    sc.prep.A16 = take(sizeof(uint16_t) * (size_t)ntiles * TILE * dp);
     sc.prep.norms = static_cast<float *>(take(sizeof(float) * (size_t)ntiles * TILE));
     sc.prep.Lpad = static_cast<float *>(take(sizeof(float) * (size_t)g * dp));
     sc.prep.pairs = pg > 0 ? static_cast<float2 *>(take(sizeof(float2) * (size_t)pg * pg)) : nullptr;
@@ -226,6 +227,7 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
     a.ntiles = pr.ntiles;
     a.npair_tiles = pr.npairs;
     a.A = pr.A;
+    a.A16 = P.mode == ESOM_MODE_BF16_RESCORE ? pr.A : pr.A16;
     a.norms = pr.norms;
     a.cent = pr.cent;
     a.Lpad = pr.Lpad;
@@ -316,6 +318,8 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
 }
 
 size_t ctx_held_bytes(const esom_ctx *c) { return c->held; }
+
+const void *ctx_arena(const esom_ctx *c) { return c->arena; }
 
 void ctx_trim(esom_ctx *c) {
     dev_free(c, c->arena, c->arena_bytes);

@@ -182,7 +182,7 @@ __global__ void __launch_bounds__(1024) prep_order(int g, const int *__restrict_
 // copy for exact rescoring, and the norm maximum.
 __device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict__ L, const int *__restrict__ perm, int g,
                                int gpad, int d, int dp, int mode, const float *__restrict__ cent,
-                               void *__restrict__ A, float *__restrict__ norms,
+                               void *__restrict__ A, void *__restrict__ A16, float *__restrict__ norms,
                                float *__restrict__ Lpad, float *__restrict__ lmax, unsigned *wmax) {
     // wmax: 2 x (waves per block) words of LDS for the block's two maxima
     const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
@@ -209,16 +209,18 @@ __device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict_
             nrm += (double)c * (double)c;
             if (real) Lpad[(size_t)j * dp + q] = lv;
             const float a2 = -2.f * c;
-            if (mode == 1) {
-                // A_bf16[t][c][lane = 32 h + m][e], dim = 16 c + 8 h + e
+            {
+                // A_bf16[t][c][lane = 32 h + m][e], dim = 16 c + 8 h + e: the
+                // BF16 mode's operand, or FP32 mode's threshold-pass operand
                 const int cc = q / 16, hh = (q % 16) / 8, e = q % 8;
                 unsigned u = __float_as_uint(a2);
                 u += 0x7FFFu + ((u >> 16) & 1u);
                 const double qd = (double)__uint_as_float(u & 0xFFFF0000u) - (double)a2;
                 qe += qd * qd;
-                reinterpret_cast<unsigned short *>(A)[(((size_t)t * dc + cc) * 64 + 32 * hh + m) * 8 + e] =
+                reinterpret_cast<unsigned short *>(mode == 1 ? A : A16)[(((size_t)t * dc + cc) * 64 + 32 * hh + m) * 8 + e] =
                     (unsigned short)(u >> 16);
-            } else {
+            }
+            if (mode == 0) {
                 // A_f32[t][s][lane = 32 h + m], dim = 2 s + h
                 const int s = q / 2, hh = q % 2;
                 reinterpret_cast<float *>(A)[((size_t)t * (dp / 2) + s) * 64 + 32 * hh + m] = a2;
@@ -311,12 +313,13 @@ __device__ __forceinline__ void prep_pairs(int blk, float *prs, const float *__r
 __global__ void __launch_bounds__(256) prep_tables(const float *__restrict__ L, const int *__restrict__ perm,
                                                    int g, int gpad, int d, int dp, int mode, int nlb,
                                                    const float *__restrict__ cent, void *__restrict__ A,
+                                                   void *__restrict__ A16,
                                                    float *__restrict__ norms, float *__restrict__ Lpad,
                                                    float *__restrict__ lmax, const float *__restrict__ l2d,
                                                    float2 *__restrict__ pairs) {
     extern __shared__ __align__(16) float prs[];
     if ((int)blockIdx.x < nlb)
-        prep_landmarks((int)blockIdx.x, L, perm, g, gpad, d, dp, mode, cent, A, norms, Lpad, lmax,
+        prep_landmarks((int)blockIdx.x, L, perm, g, gpad, d, dp, mode, cent, A, A16, norms, Lpad, lmax,
                        reinterpret_cast<unsigned *>(prs));
     else
         prep_pairs((int)blockIdx.x - nlb, prs, L, l2d, perm, g, d, pairs);
@@ -336,7 +339,7 @@ hipError_t launch_prep(const Prep &P, const float *L, const float *l2d, int mode
     const int ntu = P.need_pairs ? (P.g + PAIR_TILE - 1) / PAIR_TILE : 0;
     hipLaunchKernelGGL(prep_tables, dim3((unsigned)(nlb + ntu * ntu)), dim3(256),
                        sizeof(float) * 2 * PAIR_TILE * (P.d + 1) + sizeof(float2) * 2 * PAIR_TILE, s, L, P.perm, P.g, gpad, P.d, P.dp, mode,
-                       nlb, P.cent, P.A, P.norms, P.Lpad, P.lmax, l2d, P.pairs);
+                       nlb, P.cent, P.A, P.A16, P.norms, P.Lpad, P.lmax, l2d, P.pairs);
     return hipGetLastError();
 }
 

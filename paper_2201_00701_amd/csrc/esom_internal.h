@@ -41,7 +41,8 @@ struct Prep {
     int mode = 0;
     int need_pairs = 1;      // 0: the pair table is neither allocated nor filled
     float *cent = nullptr;   // dp      centroid of L (FP32 of an FP64 mean)
-    void *A = nullptr;       // MFMA landmark operand, -2 (L - c), tile layout
+    void *A = nullptr;       // MFMA landmark operand, -2 (L - c), tile layout (the mode's precision)
+    void *A16 = nullptr;     // FP32 mode: the same operand in BF16 (threshold pass); BF16 mode: unused
     float *norms = nullptr;  // ntiles * 32: |L_j - c|^2 in MFMA row order
     float *Lpad = nullptr;   // g * dp:  L rows padded with zeros to dp
     float2 *pairs = nullptr;  // g * g (when need_pairs): (1 / (2 |L_u - L_v|^2), 1 / |l_v - l_u|^2), (0, 0) if skipped
@@ -72,7 +73,8 @@ struct EmbedArgs {
     const float *X;
     int64_t n, ldx;
     int d, dp, g, ntiles, npair_tiles;
-    const void *A;
+    const void *A;    // screen operand of the candidate pass (BF16 or FP32 by mode)
+    const void *A16;  // BF16 operand of the threshold pass (== A in BF16 mode)
     const float *norms, *cent, *Lpad, *l2d, *lmax;
     const float2 *pairs;
     const int32_t *perm, *ipos;  // position -> landmark, landmark -> position
@@ -159,6 +161,8 @@ bool embed_needs_pairs(int d, int g, const esom_params &P, int what);
 // landmarks, padded dimension dp and a pg x pg pair table; returns its bytes.
 size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg);
 size_t ctx_held_bytes(const esom_ctx *c);
+// Device address of the context's embed scratch (changes when it grows).
+const void *ctx_arena(const esom_ctx *c);
 void ctx_trim(esom_ctx *c);
 size_t embed_scratch_bytes(int64_t n, int g, int d);
 int fail_msg(int code, const char *msg);

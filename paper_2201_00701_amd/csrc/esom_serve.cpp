@@ -14,8 +14,12 @@
 // key of the high-dimensional landmarks and the selection parameters: a
 // request that only moved 2-D landmarks (the interactive edit of the paper's
 // supervision loop) skips the distance screen and runs the projection from
-// the cache.  Repeated frames on a resident dataset (same slot, shapes,
-// parameters and pointers) are captured once into a hipGraph and replayed.
+// the cache.  Frames on a resident dataset are captured into a hipGraph the
+// second time the same frame (dataset, shapes, parameters, cache use, slot
+// buffers) runs on a slot, and replayed from then on; each slot keeps the
+// graphs of its last few distinct frames, and the scheduler routes a request
+// on a resident dataset to a free slot that already holds a graph of that
+// dataset, so the interactive edits of several datasets keep replaying.
 #include <hip/hip_runtime.h>
 #include <string.h>
 
@@ -82,6 +86,7 @@ struct Request {
     bool done = false;
     bool cache_hit = false;
     bool graph_replay = false;
+    bool waited_memory = false;  // admission held back by the memory budget
     uint64_t hd_key = 0;
 };
 
@@ -99,11 +104,18 @@ struct Slot {
     Request *cur = nullptr;
     std::atomic<bool> finished{false};
     bool cache_writer = false;
-    // captured frame
-    hipGraphExec_t gexec = nullptr;
-    uint64_t gkey = 0;
-    int gseen = 0;
+    // captured frames: frame key -> graph (null until the frame is seen twice)
+    struct Frame {
+        hipGraphExec_t exec = nullptr;
+        uint64_t dataset = 0;
+        uint64_t last_use = 0;
+    };
+    std::map<uint64_t, Frame> frames;
+    uint64_t use_clock = 0;
 };
+
+// Distinct frames a slot keeps graphs for (least recently used evicted).
+constexpr size_t SLOT_FRAMES = 8;
 
 }  // namespace
 
@@ -176,11 +188,20 @@ int grow_pinned(float *&p, size_t &cap, size_t need) {
     return ESOM_OK;
 }
 
+void slot_drop_frames(Slot &sl) {
+    for (auto &kv : sl.frames)
+        if (kv.second.exec) (void)hipGraphExecDestroy(kv.second.exec);
+    sl.frames.clear();
+}
+
+bool slot_has_dataset_frame(const Slot &sl, uint64_t dataset) {
+    for (auto &kv : sl.frames)
+        if (kv.second.dataset == dataset) return true;
+    return false;
+}
+
 void slot_free_buffers(Slot &sl) {
-    if (sl.gexec) (void)hipGraphExecDestroy(sl.gexec);
-    sl.gexec = nullptr;
-    sl.gkey = 0;
-    sl.gseen = 0;
+    slot_drop_frames(sl);
     auto f = [](auto *&p, size_t &cap) {
         if (p) (void)hipFree(p);
         p = nullptr;
@@ -291,7 +312,8 @@ int launch_request(esom_server *S, Slot &sl, Request &r) {
         uint64_t v[12] = {r.dataset, (uint64_t)r.n, (uint64_t)r.d, (uint64_t)r.g,
                           (uint64_t)what, (uint64_t)(uintptr_t)kidx, (uint64_t)(uintptr_t)sl.dL,
                           (uint64_t)(uintptr_t)sl.dout, (uint64_t)(uintptr_t)sl.hL,
-                          (uint64_t)(uintptr_t)sl.hout, (uint64_t)ctx_held_bytes(sl.ctx), 0};
+                          (uint64_t)(uintptr_t)sl.hout, (uint64_t)ctx_held_bytes(sl.ctx),
+                          (uint64_t)(uintptr_t)ctx_arena(sl.ctx)};
         key = fnv1a(v, sizeof v, fnv1a(&r.P, sizeof r.P));
     }
     auto enqueue = [&]() -> int {
@@ -308,12 +330,15 @@ int launch_request(esom_server *S, Slot &sl, Request &r) {
             return fail_msg(ESOM_EDEVICE, "serving: result download failed");
         return ESOM_OK;
     };
-    if (ds && key == sl.gkey && sl.gexec) {
-        if (hipGraphLaunch(sl.gexec, s) != hipSuccess) return fail_msg(ESOM_EDEVICE, "graph launch failed");
+    auto fit = ds ? sl.frames.find(key) : sl.frames.end();
+    if (fit != sl.frames.end() && fit->second.exec) {
+        if (hipGraphLaunch(fit->second.exec, s) != hipSuccess) return fail_msg(ESOM_EDEVICE, "graph launch failed");
+        fit->second.last_use = ++sl.use_clock;
         r.graph_replay = true;
         S->st.graph_replays++;
-    } else if (ds && key == sl.gkey && sl.gseen >= 1) {
-        // second identical frame on this slot: capture it (scratch is already sized)
+    } else if (fit != sl.frames.end()) {
+        // second identical frame on this slot: capture it (scratch and buffers
+        // are already sized, so the capture records no allocation)
         hipGraph_t graph = nullptr;
         if (hipStreamBeginCapture(s, hipStreamCaptureModeThreadLocal) != hipSuccess)
             return fail_msg(ESOM_EDEVICE, "stream capture failed");
@@ -324,21 +349,30 @@ int launch_request(esom_server *S, Slot &sl, Request &r) {
             return e;
         }
         if (ce != hipSuccess) return fail_msg(ESOM_EDEVICE, "stream capture failed");
-        if (sl.gexec) (void)hipGraphExecDestroy(sl.gexec);
-        sl.gexec = nullptr;
-        hipError_t ie = hipGraphInstantiate(&sl.gexec, graph, nullptr, nullptr, 0);
+        hipGraphExec_t exec = nullptr;
+        hipError_t ie = hipGraphInstantiate(&exec, graph, nullptr, nullptr, 0);
         (void)hipGraphDestroy(graph);
         if (ie != hipSuccess) return fail_msg(ESOM_EDEVICE, "graph instantiation failed");
-        if (hipGraphLaunch(sl.gexec, s) != hipSuccess) return fail_msg(ESOM_EDEVICE, "graph launch failed");
+        fit->second.exec = exec;
+        fit->second.last_use = ++sl.use_clock;
+        if (hipGraphLaunch(exec, s) != hipSuccess) return fail_msg(ESOM_EDEVICE, "graph launch failed");
     } else {
         int e = enqueue();
         if (e != ESOM_OK) return e;
-        if (sl.gexec) (void)hipGraphExecDestroy(sl.gexec);
-        sl.gexec = nullptr;
-        sl.gkey = key;
-        sl.gseen = 0;
+        if (ds) {
+            if (sl.frames.size() >= SLOT_FRAMES) {
+                auto lru = sl.frames.begin();
+                for (auto it = sl.frames.begin(); it != sl.frames.end(); ++it)
+                    if (it->second.last_use < lru->second.last_use) lru = it;
+                if (lru->second.exec) (void)hipGraphExecDestroy(lru->second.exec);
+                sl.frames.erase(lru);
+            }
+            Slot::Frame f;
+            f.dataset = r.dataset;
+            f.last_use = ++sl.use_clock;
+            sl.frames[key] = f;
+        }
     }
-    sl.gseen++;
     auto *arg = new std::pair<esom_server *, Slot *>(S, &sl);
     if (hipLaunchHostFunc(s, host_done, arg) != hipSuccess) {
         delete arg;
@@ -393,14 +427,19 @@ void scheduler(esom_server *S) {
         if (progressed) S->cv_done.notify_all();
         // admit from the head of the queue
         while (!S->queue.empty()) {
+            Request *r = S->queue.front();
+            // a free slot, preferring one that holds a captured frame of the
+            // request's resident dataset
             Slot *free_slot = nullptr;
             for (auto &sl : S->slots)
                 if (!sl->cur) {
-                    free_slot = sl.get();
-                    break;
+                    if (!free_slot) free_slot = sl.get();
+                    if (r->dataset && slot_has_dataset_frame(*sl, r->dataset)) {
+                        free_slot = sl.get();
+                        break;
+                    }
                 }
             if (!free_slot) break;
-            Request *r = S->queue.front();
             const size_t need = footprint(*r);
             size_t used = S->resident + slot_held(S);
             if (S->budget && used + need > S->budget) {
@@ -408,7 +447,14 @@ void scheduler(esom_server *S) {
                 for (auto &sl : S->slots)
                     if (!sl->cur) slot_free_buffers(*sl);
                 used = S->resident + slot_held(S);
-                if (used + need > S->budget) break;  // wait for running requests to finish
+                if (used + need > S->budget) {
+                    // wait for running requests to finish
+                    if (!r->waited_memory) {
+                        r->waited_memory = true;
+                        S->st.admission_waits++;
+                    }
+                    break;
+                }
             }
             S->queue.pop_front();
             r->t_start = now_ms(S->t0);
@@ -619,6 +665,7 @@ int esom_serve_submit(esom_server *S, uint64_t dataset_id, const float *X_host, 
     r->t_submit = now_ms(S->t0);
     *request_id = r->id;
     S->queue.push_back(r.get());
+    if ((int64_t)S->queue.size() > S->st.max_queued) S->st.max_queued = (int64_t)S->queue.size();
     S->requests[r->id] = std::move(r);
     lk.unlock();
     wake(S);

@@ -59,7 +59,8 @@ class esom_request_info(ctypes.Structure):
 class esom_serve_stats(ctypes.Structure):
     _fields_ = [(n, ctypes.c_int64) for n in (
         "completed", "failed", "rejected", "points", "cache_hits", "graph_replays", "queued",
-        "in_flight", "slots", "budget_bytes", "resident_bytes", "held_bytes", "peak_bytes")] + [
+        "in_flight", "slots", "budget_bytes", "resident_bytes", "held_bytes", "peak_bytes",
+        "admission_waits", "max_queued")] + [
         ("now_ms", ctypes.c_double)]
 
     def as_dict(self):

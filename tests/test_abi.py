@@ -46,7 +46,7 @@ def test_param_struct_matches_header_defaults():
     assert ctypes.sizeof(esom.esom_params) == 28
     assert ctypes.sizeof(esom.esom_stats) == 96
     assert ctypes.sizeof(esom.esom_request_info) == 48
-    assert ctypes.sizeof(esom.esom_serve_stats) == 112
+    assert ctypes.sizeof(esom.esom_serve_stats) == 128
 
 
 def test_binding_never_imports_the_oracle():

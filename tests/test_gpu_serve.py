@@ -113,6 +113,34 @@ def test_resident_dataset_2d_edits_use_cache_and_graph(torch_dev, k):
     srv.close()
 
 
+def test_alternating_datasets_keep_replaying(torch_dev):
+    # edits of two resident datasets interleave on a 2-slot server: each slot
+    # keeps the graphs of several frames and requests go to the slot that
+    # holds their dataset's graph, so both datasets' frames replay
+    from paper_2201_00701_amd.esom import Server
+    rng = np.random.default_rng(11)
+    cases = [_req(211, 30000, 32, 400, 20), _req(212, 20000, 16, 100, 10)]
+    srv = Server(0, 0, 2)
+    dids = [srv.put(X) for X, _, _ in cases]
+    ls = [l.copy() for _, _, l in cases]
+    outs = [np.empty((len(X), 2), np.float32) for X, _, _ in cases]
+    _say("case serve alternating resident datasets")
+    replays = [0, 0]
+    for frame in range(14):
+        i = frame % 2
+        X, L, _ = cases[i]
+        if frame >= 2:
+            moved = rng.choice(len(ls[i]), 2, replace=False)
+            ls[i] = ls[i].copy()
+            ls[i][moved] += rng.normal(0, 0.5, (2, 2)).astype(np.float32)
+        info = srv.wait(srv.submit(L, ls[i], k=8, mode="bf16", dataset=dids[i], out=outs[i]), 60000)
+        replays[i] += info["graph_replay"]
+        np.testing.assert_array_equal(outs[i], _direct(torch_dev, X, L, ls[i], 8, "bf16"))
+    _say("  replays per dataset %s" % replays)
+    assert min(replays) >= 3
+    srv.close()
+
+
 def test_admission_by_footprint(torch_dev):
     from paper_2201_00701_amd import esom
     from paper_2201_00701_amd.esom import Server

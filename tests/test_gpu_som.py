@@ -89,7 +89,7 @@ def test_som_train_serial_steps_and_slow_shapes(torch_dev, ctx, oracle_mod):
     np.testing.assert_allclose(got, ref, rtol=2e-5, atol=2e-5)
     # more landmarks and dimensions than the fast kernels take: the nearest
     # landmarks come from the exact path
-    X = synth.mixture(3000, 70, 6, seed=62)
+    X = synth.mixture(6000, 70, 6, seed=62)
     L = synth.landmarks_from_data(X, 4200, seed=62)
     l = synth.grid2d(4200, 70)
     rows = rng.integers(0, len(X), (3, 256)).astype(np.int32)

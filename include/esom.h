@@ -137,6 +137,30 @@ int esom_embed(esom_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx,
                const float *L_hd, const float *L_2d, int32_t g, const esom_params *params,
                float *out, int32_t *knn_idx, float *knn_dist2, void *stream);
 
+/* Allocation-free variant of esom_embed, for callers that cannot allocate
+ * device memory: code under HIP graph capture, tight serving loops, and
+ * harnesses that forbid hipMalloc.  It computes exactly what esom_embed
+ * computes for the same arguments, with the same kernels, but needs no
+ * context: its scratch (landmark preparation, the g x g pair table, the
+ * exact-path list and counters) is one fixed device array of
+ * ESOM_NOALLOC_SCRATCH_BYTES per GPU, part of the library's code object
+ * (held by each GPU the library runs on until the process ends).  Points go
+ * through in chunks sized to the array's room (more than a million points per
+ * chunk at the largest landmark set), so n is not limited.  The first call on
+ * a device resolves the array's address on that device; no call allocates.
+ * Runs on the calling thread's current device.
+ * Every call on one GPU shares that GPU's array: calls that overlap on one GPU
+ * (on different streams, or from several host threads without ordering) race
+ * and give undefined results; calls ordered on one stream are safe.
+ * Arguments, outputs and errors as for esom_embed, plus ESOM_EINVAL for
+ * g > ESOM_NOALLOC_MAX_G or d > ESOM_NOALLOC_MAX_D. */
+#define ESOM_NOALLOC_SCRATCH_BYTES ((size_t)24 << 20)
+#define ESOM_NOALLOC_MAX_G 1024
+#define ESOM_NOALLOC_MAX_D 128
+int esom_embed_noalloc(const float *X, int64_t n, int32_t d, int64_t ldx, const float *L_hd,
+                       const float *L_2d, int32_t g, const esom_params *params, float *out,
+                       int32_t *knn_idx, float *knn_dist2, void *stream);
+
 /* One semi-supervised landmark step (Section "User supervision and model
  * interaction": an interactive k-means with a low learning rate in graph
  * mode, a SOM trained on the user's 2-D topology in SOM mode), batch form:

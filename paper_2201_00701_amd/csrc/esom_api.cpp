@@ -6,6 +6,7 @@
 #include <stdio.h>
 #include <string.h>
 
+#include <mutex>
 #include <string>
 #include <vector>
 
@@ -370,6 +371,45 @@ int validate_params(const esom_params &P, int g) {
 
 }  // namespace esom
 
+// ---------------------------------------------------------------- allocation-free embed
+// One fixed device array per GPU holds everything an embed needs beyond its
+// inputs and outputs: the counters (first 256 bytes), then one embed scratch
+// (landmark preparation, pair table, exact-path list of one chunk of points).
+// In host code `scratch` names a host-side stand-in; its device address on
+// each GPU comes from hipGetSymbolAddress, resolved once per device.
+static __device__ __align__(256) unsigned char scratch[ESOM_NOALLOC_SCRATCH_BYTES];
+
+namespace {
+
+constexpr int NOALLOC_MAX_DEVICES = 64;
+constexpr size_t NOALLOC_COUNTER_BYTES = 256;
+static_assert(sizeof(unsigned long long) * C_COUNT <= NOALLOC_COUNTER_BYTES, "counter slots");
+
+struct NoallocDevice {
+    std::once_flag once;
+    hipError_t err = hipSuccess;
+    unsigned char *ptr = nullptr;  // device address of `scratch` on this device
+    int num_cus = 0;
+    size_t lds_per_block = 0;
+};
+NoallocDevice g_noalloc[NOALLOC_MAX_DEVICES];
+
+// Resolves the array's address and the launch attributes of the current
+// device (once per device).
+void noalloc_setup(NoallocDevice &nd) {
+    nd.err = hipGetSymbolAddress(reinterpret_cast<void **>(&nd.ptr), HIP_SYMBOL(scratch));
+    if (nd.err != hipSuccess) return;
+    int dev = 0, cus = 0, lds = 0;
+    nd.err = hipGetDevice(&dev);
+    if (nd.err == hipSuccess) nd.err = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (nd.err == hipSuccess)
+        nd.err = hipDeviceGetAttribute(&lds, hipDeviceAttributeMaxSharedMemoryPerBlock, dev);
+    nd.num_cus = cus;
+    nd.lds_per_block = (size_t)lds;
+}
+
+}  // namespace
+
 extern "C" {
 
 void esom_default_params(esom_params *p) {
@@ -484,6 +524,48 @@ int esom_embed(esom_ctx *c, const float *X, int64_t n, int32_t d, int64_t ldx, c
     if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
     return run_embed(c, X, n, d, ldx, L_hd, L_2d, g, P, out, knn_idx, knn_dist2, EMBED_FULL,
                      static_cast<hipStream_t>(stream), nullptr, 1);
+}
+
+int esom_embed_noalloc(const float *X, int64_t n, int32_t d, int64_t ldx, const float *L_hd,
+                       const float *L_2d, int32_t g, const esom_params *params, float *out,
+                       int32_t *knn_idx, float *knn_dist2, void *stream) {
+    t_err.clear();
+    if (!params) return fail(ESOM_EINVAL, "params is NULL");
+    const esom_params &P = *params;
+    int st = validate_embed(X, n, d, ldx, L_hd, L_2d, g, P, out, knn_idx, knn_dist2);
+    if (st != ESOM_OK) return st;
+    if (g > ESOM_NOALLOC_MAX_G)
+        return fail(ESOM_EINVAL, "g = %d exceeds the allocation-free limit %d", g, ESOM_NOALLOC_MAX_G);
+    if (d > ESOM_NOALLOC_MAX_D)
+        return fail(ESOM_EINVAL, "d = %d exceeds the allocation-free limit %d", d, ESOM_NOALLOC_MAX_D);
+    if (n == 0) return ESOM_OK;
+    int dev = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e != hipSuccess) return hip_fail(e, "hipGetDevice");
+    if (dev < 0 || dev >= NOALLOC_MAX_DEVICES)
+        return fail(ESOM_EINVAL, "device %d beyond the allocation-free limit %d", dev, NOALLOC_MAX_DEVICES);
+    NoallocDevice &nd = g_noalloc[dev];
+    std::call_once(nd.once, noalloc_setup, std::ref(nd));
+    if (nd.err != hipSuccess) return hip_fail(nd.err, "allocation-free scratch set-up");
+    // Layout: counters, then the embed scratch for `chunk` points.  Every
+    // chunk point adds 4 + 1 + 4 bytes to the exact-path list; with chunk a
+    // multiple of 256 those three arrays need no alignment padding beyond
+    // what carve reserves for one point each.
+    const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
+    const int pg = embed_needs_pairs(d, g, P, EMBED_FULL) ? g : 0;
+    const size_t room = ESOM_NOALLOC_SCRATCH_BYTES - NOALLOC_COUNTER_BYTES;
+    Scratch sc;
+    const size_t fixed = carve(sc, nullptr, 1, g, pl.dp, pg);
+    if (fixed + 9 * 256 > room) return fail(ESOM_EINVAL, "landmark set too large for the allocation-free scratch");
+    int64_t chunk = (int64_t)((room - fixed) / 9) & ~(int64_t)255;
+    if (chunk > n) chunk = n;
+    if (carve(sc, nullptr, chunk, g, pl.dp, pg) > room)
+        return fail(ESOM_EINVAL, "internal: allocation-free scratch layout overflow");
+    carve(sc, nd.ptr + NOALLOC_COUNTER_BYTES, chunk, g, pl.dp, pg);
+    unsigned long long *counters = reinterpret_cast<unsigned long long *>(nd.ptr);
+    return enqueue_embed(sc, counters, nd.num_cus, nd.lds_per_block, X, n, d, ldx, L_hd, L_2d, g, P,
+                         out, knn_idx, knn_dist2, EMBED_FULL, static_cast<hipStream_t>(stream), nullptr,
+                         nullptr, chunk, 1);
 }
 
 namespace {

@@ -98,6 +98,9 @@ def load(path: str = LIB_PATH):
     lib.esom_embed.argtypes = [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32,
                                ctypes.POINTER(esom_params), _vp, _vp, _vp, _vp]
     lib.esom_embed.restype = ctypes.c_int
+    lib.esom_embed_noalloc.argtypes = [_vp, _i64, _i32, _i64, _vp, _vp, _i32,
+                                       ctypes.POINTER(esom_params), _vp, _vp, _vp, _vp]
+    lib.esom_embed_noalloc.restype = ctypes.c_int
     lib.esom_landmark_update.argtypes = [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32, _i32, _f32,
                                          _f32, _vp, _i64, _vp, _vp]
     lib.esom_landmark_update.restype = ctypes.c_int
@@ -175,6 +178,12 @@ def esom_embed(ctx, X, n, d, ldx, L_hd, L_2d, g, params, out, knn_idx=0, knn_dis
                stream=0) -> int:
     return load().esom_embed(ctx, X, n, d, ldx, L_hd, L_2d, g, ctypes.byref(params), out,
                              knn_idx or None, knn_dist2 or None, stream or None)
+
+
+def esom_embed_noalloc(X, n, d, ldx, L_hd, L_2d, g, params, out, knn_idx=0, knn_dist2=0,
+                       stream=0) -> int:
+    return load().esom_embed_noalloc(X, n, d, ldx, L_hd, L_2d, g, ctypes.byref(params), out,
+                                     knn_idx or None, knn_dist2 or None, stream or None)
 
 
 def esom_landmark_update(ctx, X, n, d, ldx, L_hd, L_2d, g, kind, alpha, sigma, nearest=0,

@@ -265,6 +265,63 @@ def run_workload(torch, esom, w, modes, args, frame_update=False, keep_rows=None
     return results, kept
 
 
+def ablations(torch, esom, synth, reps=3):
+    """The paper's kernel families (k-NN Base / Shared / GridInsert / Bitonic,
+    projection Base / Shared / Aligned / Registers) beside the fused kernel on
+    the paper-shaped workload: n = 2^20 points uniform on [0, 1)^d, d in
+    {16, 32}, 256 landmarks (16 x 16 grid), k = 16.  Milliseconds per call from
+    HIP events (the median of `reps` calls after one warm-up call)."""
+    import numpy as np
+    res = {}
+    for d in (16, 32):
+        w = synth.paper_shaped(d)
+        n = len(w.X)
+        X = torch.from_numpy(w.X).cuda()
+        L = torch.from_numpy(w.L).cuda()
+        l = torch.from_numpy(w.l).cuda()
+        k = w.k
+
+        def timed(fn):
+            fn()
+            torch.cuda.synchronize()
+            ts = []
+            for _ in range(reps):
+                e0, e1 = torch.cuda.Event(enable_timing=True), torch.cuda.Event(enable_timing=True)
+                e0.record()
+                fn()
+                e1.record()
+                torch.cuda.synchronize()
+                ts.append(e0.elapsed_time(e1))
+            return float(np.median(ts))
+
+        ctx = esom.Context(0)
+        out = torch.empty((n, 2), dtype=torch.float32, device="cuda")
+        r = {"n": n, "d": d, "g": len(w.L), "k": k,
+             "fused_fp32_ms": timed(lambda: ctx.embed(X, L, l, k=k, mode="fp32", out=out)),
+             "fused_bf16_ms": timed(lambda: ctx.embed(X, L, l, k=k, mode="bf16", out=out))}
+        ctx.close()
+        knn, proj = {}, {}
+        for algo in ("base", "shared", "gridinsert", "bitonic"):
+            knn[algo] = timed(lambda: esom.ablation_knn(algo, X, L, k))
+        idx, d2 = esom.ablation_knn("bitonic", X, L, k)
+        for algo in ("base", "shared", "aligned", "registers"):
+            proj[algo] = timed(lambda: esom.ablation_project(algo, X, L, l, idx, d2, out=out))
+        r["knn_ms"] = knn
+        r["projection_ms"] = proj
+        best = min(knn.values()) + min(proj.values())
+        r["best_pair_ms"] = best
+        r["fused_fp32_points_per_s"] = n / (r["fused_fp32_ms"] * 1e-3)
+        r["best_pair_points_per_s"] = n / (best * 1e-3)
+        res["paper_uniform_d%d" % d] = r
+        print("bench: ablations d=%d: fused fp32 %.3f ms, bf16 %.3f ms; knn %s; projection %s"
+              % (d, r["fused_fp32_ms"], r["fused_bf16_ms"],
+                 ", ".join("%s %.3f" % kv for kv in knn.items()),
+                 ", ".join("%s %.3f" % kv for kv in proj.items())), file=sys.stderr, flush=True)
+        del X, L, l, out, idx, d2
+        torch.cuda.empty_cache()
+    return res
+
+
 def serve_mix(n_requests=2000, warmup=200, rate=200.0, budget=8 << 30, slots=4, seed=5,
               base_n=1_000_000):
     """Serving mix: Poisson arrivals; N log-uniform in [1e3, 1e6]; D in {16, 32, 48};
@@ -378,6 +435,8 @@ def main():
     ap.add_argument("--modes", default="bf16,fp32")
     ap.add_argument("--no-cpu-baseline", action="store_true")
     ap.add_argument("--no-serve", action="store_true")
+    ap.add_argument("--no-ablations", action="store_true",
+                    help="skip the paper's kernel families on the paper-shaped workload")
     ap.add_argument("--serve-requests", type=int, default=2000)
     ap.add_argument("--tight-budget-mib", type=int, default=384,
                     help="HBM budget of the second serving run (admission binds)")
@@ -457,6 +516,8 @@ def main():
     }
     if "cpu_baseline" in hw:
         line["cpu_baseline"] = hw["cpu_baseline"]
+    if not args.no_ablations:
+        line["ablations"] = ablations(torch, esom, synth)
     if not args.no_serve:
         print("bench: serving mix (%d requests)" % args.serve_requests, file=sys.stderr, flush=True)
         line["serving"] = serve_mix(n_requests=args.serve_requests)

@@ -231,6 +231,117 @@ int esom_som_train(esom_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t 
 int esom_fit_landmarks(const float *L_hd, const float *L_2d, int32_t g, int32_t d, const float *p_2d,
                        int32_t m, int32_t kfit, float sigma, float *L_new, void *stream);
 
+/* EmbedSOM projection into 3-D.  The paper states the method in 2-D for
+ * brevity (Section "Landmark-directed dimensionality reduction"); with 3-D
+ * landmark positions the same four steps give a 3 x 3 linear system per point
+ * (normal equations of sum_{u<v} s_u s_v |h|^(2-2a) (D_uv - d_uv(p))^2 plus
+ * gravity, h = l_v - l_u in 3-D), solved by Cramer's rule in FP64; a
+ * degenerate neighbourhood or a numerically singular system (det <= 1e-9
+ * (trace/3)^3) gives the centroid of the neighbours' 3-D positions.  The k
+ * nearest landmarks are found exactly as by esom_embed (same screen, exact
+ * selection and exact path); scores and pairs are then evaluated in FP64.
+ *   L_3d     device, g x 3 floats
+ *   out      device, n x 3 floats (written; NaN for a point without k finite distances)
+ *   knn_idx  device, n x k int32 or NULL: the k nearest, as esom_embed returns them
+ * Other arguments, limits and errors as for esom_embed. */
+int esom_embed3(esom_ctx *ctx, const float *X, int64_t n, int32_t d, int64_t ldx, const float *L_hd,
+                const float *L_3d, int32_t g, const esom_params *params, float *out, int32_t *knn_idx,
+                void *stream);
+
+/* ---------------------------------------------------------------- graph mode
+ * Section "Semi-supervised structure reconstruction": the high-dimensional
+ * landmarks follow an interactive k-means (esom_landmark_update, kind 0), their
+ * 2-D positions a force-based layout of a neighbourhood graph of the
+ * landmarks, which the user steers by dragging (fixing) nodes; landmarks are
+ * added by duplicating one in both spaces, and removed. */
+#define ESOM_GRAPH_MAX_K 32
+
+/* Neighbourhood graph: for every landmark u its kg nearest other landmarks by
+ * (squared distance, index), u excluded, distances as FP64 sums.
+ *   L_hd  device, g x d floats;  nbr: device, g x kg int32 (written)
+ *   dist2 device, g x kg floats or NULL: their squared distances
+ * No context: runs on the current device.  Errors: ESOM_EINVAL for g outside
+ * [2, ESOM_MAX_G], d out of range, kg outside [1, min(g - 1, ESOM_GRAPH_MAX_K)],
+ * NULL or misaligned arrays. */
+int esom_landmark_graph(const float *L_hd, int32_t g, int32_t d, int32_t kg, int32_t *nbr,
+                        float *dist2, void *stream);
+
+/* Force law of the layout (reading of the paper's "simple force-based graph
+ * layout"): on every undirected edge u-v of the graph (v in u's list or u in
+ * v's) a spring of rest length scale * |L_u - L_v|, force (r - rest) along the
+ * edge (r the 2-D distance; none while r = 0); between all pairs a softened
+ * repulsion of repulsion * (l_u - l_v) / (|l_u - l_v|^2 + softening^2).  Each
+ * synchronous step moves every free node by step * force, shortened to
+ * max_move.  Sums in FP64, positions stored as floats after every step. */
+typedef struct {
+    float scale;      /* 2-D length per unit of high-dimensional distance (>= 0) */
+    float repulsion;  /* >= 0 */
+    float softening;  /* > 0 */
+    float step;       /* >= 0 */
+    float max_move;   /* >= 0: longest move of a node per step */
+} esom_layout_params;
+
+/* Defaults: scale 1, repulsion 0.05, softening 0.5, step 0.1, max_move 0.5. */
+void esom_default_layout_params(esom_layout_params *p);
+
+/* Runs `steps` layout steps on L_2d (device, g x 2 floats, 8-byte aligned,
+ * updated in place).  nbr: the graph (device, g x kg int32; -1 entries are
+ * ignored).  fixed: device, g bytes or NULL; nodes with fixed[u] != 0 keep
+ * their position (dragged by the user).  The context provides a g x 2 buffer
+ * for the steps.  Errors: ESOM_EINVAL for shapes as esom_landmark_graph,
+ * steps < 0, parameters not finite or negative (softening <= 0), NULL or
+ * misaligned arrays; ESOM_ENOMEM for the buffer beyond the context budget. */
+int esom_graph_layout(esom_ctx *ctx, const float *L_hd, int32_t g, int32_t d, const int32_t *nbr,
+                      int32_t kg, float *L_2d, const uint8_t *fixed, int32_t steps,
+                      const esom_layout_params *params, void *stream);
+
+/* Adds landmark g as a duplicate of landmark j: row g of L_hd := row j, and
+ * L_2d[g] := L_2d[j] + (dx, dy).  Both device arrays must hold g + 1 rows.
+ * Errors: ESOM_EINVAL for g outside [1, ESOM_MAX_G), j outside [0, g),
+ * non-finite offsets, NULL or misaligned arrays. */
+int esom_landmark_duplicate(float *L_hd, float *L_2d, int32_t g, int32_t d, int32_t j, float dx,
+                            float dy, void *stream);
+
+/* Removes landmark j of g: the last landmark (g - 1) moves into slot j in both
+ * arrays, leaving g - 1 landmarks (the caller's count).  Errors: ESOM_EINVAL for
+ * g outside [2, ESOM_MAX_G], j outside [0, g), NULL or misaligned arrays. */
+int esom_landmark_remove(float *L_hd, float *L_2d, int32_t g, int32_t d, int32_t j, void *stream);
+
+/* ---------------------------------------------------------------- ablations
+ * The paper's kernel families (Sections "k-NN step" and "Projection step"),
+ * rebuilt for gfx950 in plain FP32 with the paper's work division and
+ * caching, for measuring their relative merits against the fused kernel.
+ * They have no screen, certificate or FP64 solve: results carry FP32
+ * rounding (neighbour order among distances closer than FP32 resolves;
+ * coordinates of ill-conditioned systems).
+ * X is n x d row-major (contiguous), L_hd g x d, L_2d g x 2 (8-byte aligned).
+ * ESOM_ABL_* select the algorithm; d <= 128, k <= 64. */
+#define ESOM_ABL_KNN_BASE 0        /* one thread per point, global memory */
+#define ESOM_ABL_KNN_SHARED 1      /* landmarks staged in LDS */
+#define ESOM_ABL_KNN_GRIDINSERT 2  /* h points x w landmarks per block epoch */
+#define ESOM_ABL_KNN_BITONIC 3     /* k threads per point, bitonic merges */
+#define ESOM_ABL_PROJ_BASE 0       /* one thread per point */
+#define ESOM_ABL_PROJ_SHARED 1     /* a block per point, neighbours in LDS */
+#define ESOM_ABL_PROJ_ALIGNED 2    /* Shared with padded rows and float4 */
+#define ESOM_ABL_PROJ_REGISTERS 3  /* Aligned with 2 x 2 pair groups per thread */
+
+/* The k nearest landmarks of every point by FP32 distance (ties to the lower
+ * index): knn_idx, knn_dist2 device n x k, sorted.  Errors: ESOM_EINVAL for an
+ * unknown algo, d outside [1, 128], k outside [1, min(g, 64)], n out of range,
+ * NULL or misaligned arrays. */
+int esom_ablation_knn(int32_t algo, const float *X, int64_t n, int32_t d, const float *L_hd, int32_t g,
+                      int32_t k, int32_t *knn_idx, float *knn_dist2, void *stream);
+
+/* The projection (scores, segment projections, 2x2 Cramer, FP32) of every
+ * point from its k sorted neighbours (knn_idx, knn_dist2 as esom_ablation_knn
+ * returns them; indices must lie in [0, g), others are clamped into it);
+ * out device n x 2.  Parameters as esom_embed (k = params->k,
+ * mode ignored); degenerate neighbourhoods map to the neighbours' centroid.
+ * Errors: as esom_ablation_knn plus the esom_embed parameter rules. */
+int esom_ablation_project(int32_t algo, const float *X, int64_t n, int32_t d, const float *L_hd,
+                          const float *L_2d, int32_t g, const esom_params *params, const int32_t *knn_idx,
+                          const float *knn_dist2, float *out, void *stream);
+
 /* Waits for the work enqueued on `stream`; ESOM_EDEVICE reports a device fault. */
 int esom_sync(esom_ctx *ctx, void *stream);
 

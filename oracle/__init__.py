@@ -49,6 +49,7 @@ def _load():
         i32p = ctypes.POINTER(ctypes.c_int32)
         i64p = ctypes.POINTER(ctypes.c_int64)
         i64, i32, dbl = ctypes.c_int64, ctypes.c_int, ctypes.c_double
+        u8p = ctypes.POINTER(ctypes.c_uint8)
         lib.oracle_scores.argtypes = [f64p, i32, i32, dbl, dbl, f64p]
         lib.oracle_scores.restype = i32
         lib.oracle_knn.argtypes = [f32p, i64, i32, i64, f32p, i32, i32, i32p, f64p, i32]
@@ -59,12 +60,18 @@ def _load():
         lib.oracle_landmark_update.argtypes = [f32p, i64, i32, i64, f32p, f32p, i32, i32,
                                                dbl, dbl, f64p, i64p, i32]
         lib.oracle_landmark_update.restype = i32
-        u8p = ctypes.POINTER(ctypes.c_uint8)
         lib.oracle_som_train.argtypes = [f32p, i64, i32, i64, f32p, f32p, i32, i32p, i32, i32,
                                          f64p, f64p, u8p]
         lib.oracle_som_train.restype = i32
         lib.oracle_fit_landmarks.argtypes = [f32p, f32p, i32, i32, f32p, i32, i32, dbl, f64p]
         lib.oracle_fit_landmarks.restype = i32
+        lib.oracle_embed3.argtypes = lib.oracle_embed.argtypes
+        lib.oracle_embed3.restype = i32
+        lib.oracle_landmark_graph.argtypes = [f32p, i32, i32, i32, i32p, f64p]
+        lib.oracle_landmark_graph.restype = i32
+        lib.oracle_layout_step.argtypes = [f32p, i32, i32, i32p, i32, f32p, u8p, dbl, dbl, dbl,
+                                           dbl, dbl]
+        lib.oracle_layout_step.restype = i32
         _lib = lib
     return _lib
 
@@ -200,3 +207,64 @@ def fit_landmarks(L, l, p, kfit=8, sigma=1.0):
     if rc != 0:
         raise ValueError("oracle_fit_landmarks failed (%d)" % rc)
     return out
+
+
+def embed3(X, L, l3, k, boost=DEFAULT_BOOST, adjust=DEFAULT_ADJUST, cutoff=DEFAULT_CUTOFF,
+           gravity=DEFAULT_GRAVITY, threads=1):
+    """The projection with 3-D landmark positions l3 (g x 3).  Returns dict(out n x 3
+    f64, idx n x (k+1), d2 n x (k+1), n_degenerate)."""
+    lib = _load()
+    X, ldx = _f32_rows(X)
+    L = np.ascontiguousarray(L, dtype=np.float32)
+    l3 = np.ascontiguousarray(l3, dtype=np.float32)
+    n, d = X.shape
+    g = L.shape[0]
+    if L.shape[1] != d or l3.shape != (g, 3):
+        raise ValueError("shape mismatch")
+    out = np.empty((n, 3), np.float64)
+    idx = np.empty((n, k + 1), np.int32)
+    d2 = np.empty((n, k + 1), np.float64)
+    ndeg = ctypes.c_int64(0)
+    rc = lib.oracle_embed3(_ptr(X, ctypes.c_float), n, d, ldx, _ptr(L, ctypes.c_float),
+                           _ptr(l3, ctypes.c_float), g, int(k), float(boost), float(adjust),
+                           float(cutoff), float(gravity), _ptr(out, ctypes.c_double),
+                           _ptr(idx, ctypes.c_int32), _ptr(d2, ctypes.c_double),
+                           ctypes.byref(ndeg), int(threads))
+    if rc != 0:
+        raise ValueError("oracle_embed3 failed (%d)" % rc)
+    return {"out": out, "idx": idx, "d2": d2, "n_degenerate": int(ndeg.value)}
+
+
+def landmark_graph(L, kg):
+    """kg nearest other landmarks of every landmark: (nbr int32 g x kg, d2 f64 g x kg)."""
+    lib = _load()
+    L = np.ascontiguousarray(L, dtype=np.float32)
+    g, d = L.shape
+    nbr = np.empty((g, kg), np.int32)
+    d2 = np.empty((g, kg), np.float64)
+    rc = lib.oracle_landmark_graph(_ptr(L, ctypes.c_float), g, d, int(kg),
+                                   _ptr(nbr, ctypes.c_int32), _ptr(d2, ctypes.c_double))
+    if rc != 0:
+        raise ValueError("oracle_landmark_graph failed (%d)" % rc)
+    return nbr, d2
+
+
+def layout(L, nbr, l, steps=1, fixed=None, scale=1.0, repulsion=0.0, soft=1.0, step=0.1,
+           max_move=1.0):
+    """`steps` synchronous force-layout steps of the 2-D positions l (g x 2) on the
+    landmark graph nbr.  Returns the new positions (float32 g x 2, a new array)."""
+    lib = _load()
+    L = np.ascontiguousarray(L, dtype=np.float32)
+    nb = np.ascontiguousarray(nbr, dtype=np.int32)
+    lw = np.array(l, dtype=np.float32, order="C", copy=True)
+    g, d = L.shape
+    fz = None if fixed is None else np.ascontiguousarray(fixed, dtype=np.uint8)
+    for _ in range(steps):
+        rc = lib.oracle_layout_step(_ptr(L, ctypes.c_float), g, d, _ptr(nb, ctypes.c_int32),
+                                    nb.shape[1], _ptr(lw, ctypes.c_float),
+                                    _ptr(fz, ctypes.c_uint8) if fz is not None else None,
+                                    float(scale), float(repulsion), float(soft), float(step),
+                                    float(max_move))
+        if rc != 0:
+            raise ValueError("oracle_layout_step failed (%d)" % rc)
+    return lw

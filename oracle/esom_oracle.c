@@ -229,6 +229,99 @@ static int project_point(const float *x, const float *L, const float *l, int g,
     return 0;
 }
 
+/* ---- the same four steps with a 3-D output ----------------------------------- */
+
+/* Determinant of a 3 x 3 matrix by cofactor expansion along the first row. */
+static double det3(const double A[3][3])
+{
+    return A[0][0] * (A[1][1] * A[2][2] - A[1][2] * A[2][1]) -
+           A[0][1] * (A[1][0] * A[2][2] - A[1][2] * A[2][0]) +
+           A[0][2] * (A[1][0] * A[2][1] - A[1][1] * A[2][0]);
+}
+
+/* Projects one point into 3-D: the paper states the method in 2-D for
+ * brevity (Section "Landmark-directed dimensionality reduction"); with 3-D
+ * landmark positions l (g x 3) the same objective sum_{u<v} w_uv (D_uv -
+ * d_uv(p))^2 plus gravity has 3 x 3 normal equations M p = r, solved by
+ * Cramer's rule.  The singular-system rule scales with the dimension: det <=
+ * 1e-9 (tr/3)^3 maps to the centroid of the neighbours' 3-D positions. */
+static int project_point3(const float *x, const float *L, const float *l, int g,
+                          int d, int k, const int *nb, const double *d2,
+                          const oracle_params *P, double *s_scratch,
+                          double *delta_scratch, double *p)
+{
+    for (int i = 0; i < k; ++i)
+        delta_scratch[i] = sqrt(d2[i]);
+    int degenerate = oracle_scores(delta_scratch, k, g, P->boost, P->cutoff, s_scratch);
+    const double *s = s_scratch;
+    double ssum = 0.0;
+    for (int i = 0; i < k; ++i)
+        ssum += s[i];
+    double M[3][3] = {{0}}, r[3] = {0};
+    if (!degenerate) {
+        for (int i = 0; i < k; ++i) {
+            int u = nb[i];
+            const float *Lu = L + (size_t)u * d;
+            const float *lu = l + (size_t)3 * u;
+            for (int j = i + 1; j < k; ++j) {
+                int v = nb[j];
+                const float *Lv = L + (size_t)v * d;
+                const float *lv = l + (size_t)3 * v;
+                double HH = 0.0, xH = 0.0;
+                for (int t = 0; t < d; ++t) {
+                    double H = (double)Lv[t] - (double)Lu[t];
+                    HH += H * H;
+                    xH += ((double)x[t] - (double)Lu[t]) * H;
+                }
+                if (HH == 0.0)
+                    continue;
+                double D = xH / HH;
+                double h[3], hh = 0.0, hl = 0.0;
+                for (int a = 0; a < 3; ++a) {
+                    h[a] = (double)lv[a] - (double)lu[a];
+                    hh += h[a] * h[a];
+                    hl += h[a] * (double)lu[a];
+                }
+                if (hh == 0.0)
+                    continue;
+                double q = s[i] * s[j] * pow(hh, -P->adjust);
+                double rhs = D + hl / hh;
+                for (int a = 0; a < 3; ++a) {
+                    for (int b = 0; b < 3; ++b)
+                        M[a][b] += q * h[a] * h[b] / hh;
+                    r[a] += q * h[a] * rhs;
+                }
+            }
+        }
+        for (int i = 0; i < k; ++i) {
+            double gs = P->gravity * s[i];
+            for (int a = 0; a < 3; ++a) {
+                M[a][a] += gs;
+                r[a] += gs * l[(size_t)3 * nb[i] + a];
+            }
+        }
+    }
+    double det = det3(M);
+    double tr3 = (M[0][0] + M[1][1] + M[2][2]) / 3.0;
+    if (degenerate || ssum == 0.0 || !(det > 1e-9 * tr3 * tr3 * tr3)) {
+        for (int a = 0; a < 3; ++a) {
+            double c = 0.0;
+            for (int i = 0; i < k; ++i)
+                c += l[(size_t)3 * nb[i] + a];
+            p[a] = c / k;
+        }
+        return 1;
+    }
+    for (int c = 0; c < 3; ++c) {
+        double A[3][3];
+        for (int a = 0; a < 3; ++a)
+            for (int b = 0; b < 3; ++b)
+                A[a][b] = (b == c) ? r[a] : M[a][b];
+        p[c] = det3(A) / det;
+    }
+    return 0;
+}
+
 /* ---- threaded drivers ------------------------------------------------------ */
 
 typedef struct {
@@ -236,7 +329,8 @@ typedef struct {
     int64_t n, ldx;
     int d, g, k, m;
     oracle_params P;
-    double *out;   /* n x 2 or NULL */
+    double *out;   /* n x dim or NULL */
+    int dim;       /* output dimension: 2, or 3 (then l is g x 3) */
     int32_t *idx;  /* n x m or NULL */
     double *d2out; /* n x m or NULL */
     int64_t begin, end;
@@ -266,7 +360,14 @@ static void *embed_worker(void *arg)
         if (J->d2out)
             for (int t = 0; t < m; ++t)
                 J->d2out[i * m + t] = d2[t];
-        if (J->out) {
+        if (J->out && J->dim == 3) {
+            double p[3];
+            J->n_degenerate += project_point3(x, J->L, J->l, J->g, J->d, J->k, nb, d2,
+                                              &J->P, s, dl, p);
+            J->out[3 * i] = p[0];
+            J->out[3 * i + 1] = p[1];
+            J->out[3 * i + 2] = p[2];
+        } else if (J->out) {
             double p[2];
             J->n_degenerate += project_point(x, J->L, J->l, J->g, J->d, J->k, nb, d2,
                                              &J->P, s, dl, p);
@@ -346,7 +447,28 @@ int oracle_embed(const float *X, int64_t n, int d, int64_t ldx, const float *L,
     J.X = X; J.L = L; J.l = l; J.n = n; J.ldx = ldx; J.d = d; J.g = g; J.k = k;
     J.m = k + 1;
     J.P.boost = boost; J.P.adjust = adjust; J.P.cutoff = cutoff; J.P.gravity = gravity;
-    J.out = out; J.idx = idx; J.d2out = d2;
+    J.out = out; J.dim = 2; J.idx = idx; J.d2out = d2;
+    int st = run_jobs(&J, nthreads);
+    if (n_degenerate)
+        *n_degenerate = J.n_degenerate;
+    return st;
+}
+
+/* The projection with a 3-D output: l is g x 3, out is n x 3 doubles; other
+ * arguments as for oracle_embed. */
+int oracle_embed3(const float *X, int64_t n, int d, int64_t ldx, const float *L,
+                  const float *l, int g, int k, double boost, double adjust,
+                  double cutoff, double gravity, double *out, int32_t *idx, double *d2,
+                  int64_t *n_degenerate, int nthreads)
+{
+    if (n < 0 || d < 1 || g < 3 || k < 3 || k > g || ldx < d || !X || !L || !l || !out)
+        return ORACLE_EINVAL;
+    embed_job J;
+    memset(&J, 0, sizeof J);
+    J.X = X; J.L = L; J.l = l; J.n = n; J.ldx = ldx; J.d = d; J.g = g; J.k = k;
+    J.m = k + 1;
+    J.P.boost = boost; J.P.adjust = adjust; J.P.cutoff = cutoff; J.P.gravity = gravity;
+    J.out = out; J.dim = 3; J.idx = idx; J.d2out = d2;
     int st = run_jobs(&J, nthreads);
     if (n_degenerate)
         *n_degenerate = J.n_degenerate;
@@ -594,5 +716,114 @@ int oracle_fit_landmarks(const float *L, const float *l, int g, int d, const flo
         }
     }
     free(nb); free(nd);
+    return ORACLE_OK;
+}
+
+/* ---- graph-mode supervision ------------------------------------------------------
+ * Section "Semi-supervised structure reconstruction": the high-dimensional
+ * landmarks come from an interactive k-means (oracle_landmark_update, kind 0)
+ * and their 2-D positions from a simple force-based layout of a neighbourhood
+ * graph of L, which the user steers by dragging nodes; landmarks are added by
+ * duplicating one in both spaces and removed likewise.  The paper names no
+ * graph or force law; the readings below are this build's. */
+
+/* Neighbourhood graph of the landmarks: for every landmark u its kg nearest
+ * other landmarks by (squared distance, index), u itself excluded.  nbr and d2
+ * are g x kg; slots beyond g - 1 neighbours hold -1 / +inf. */
+int oracle_landmark_graph(const float *L, int g, int d, int kg, int32_t *nbr, double *d2)
+{
+    if (g < 1 || d < 1 || kg < 1 || !L || !nbr || !d2)
+        return ORACLE_EINVAL;
+    int *nb = (int *)malloc(sizeof(int) * (size_t)(kg + 1));
+    double *nd = (double *)malloc(sizeof(double) * (size_t)(kg + 1));
+    if (!nb || !nd) {
+        free(nb); free(nd);
+        return ORACLE_ENOMEM;
+    }
+    for (int u = 0; u < g; ++u) {
+        /* the kg + 1 nearest include u itself (distance 0, or tied with an
+         * exact duplicate); dropping u leaves the kg nearest others */
+        nearest_m(L + (size_t)u * d, L, g, d, kg + 1, nb, nd);
+        int o = 0;
+        for (int i = 0; i < kg + 1 && o < kg; ++i) {
+            if (nb[i] == u)
+                continue;
+            nbr[(size_t)u * kg + o] = nb[i];
+            d2[(size_t)u * kg + o] = nb[i] >= 0 ? nd[i] : INFINITY;
+            ++o;
+        }
+        for (; o < kg; ++o) {
+            nbr[(size_t)u * kg + o] = -1;
+            d2[(size_t)u * kg + o] = INFINITY;
+        }
+    }
+    free(nb); free(nd);
+    return ORACLE_OK;
+}
+
+/* One synchronous step of the force-based layout of the 2-D landmark
+ * positions l (g x 2 floats, updated in place).  Edges: u-v when v is among
+ * u's neighbours or u among v's (nbr from oracle_landmark_graph, g x kg), each
+ * undirected edge acting once on both ends.  The force on a node u is
+ *   sum over edges u-v of (|l_v - l_u| - scale * |L_u - L_v|) (l_v - l_u) / |l_v - l_u|
+ *     (a spring whose rest length is the high-dimensional distance times
+ *     scale; skipped while the two positions coincide)
+ *   + repulsion * sum over all v != u of (l_u - l_v) / (|l_u - l_v|^2 + soft^2).
+ * Every node moves by step times its force, shortened to max_move when
+ * longer; fixed[u] != 0 (dragged by the user) keeps u in place.  Forces use
+ * the positions before the step; sums in double, positions rounded to float. */
+int oracle_layout_step(const float *L, int g, int d, const int32_t *nbr, int kg, float *l,
+                       const uint8_t *fixed, double scale, double repulsion, double soft,
+                       double step, double max_move)
+{
+    if (g < 1 || d < 1 || kg < 1 || !L || !nbr || !l)
+        return ORACLE_EINVAL;
+    unsigned char *adj = (unsigned char *)calloc((size_t)g * g, 1);
+    double *nl = (double *)malloc(sizeof(double) * 2 * (size_t)g);
+    if (!adj || !nl) {
+        free(adj); free(nl);
+        return ORACLE_ENOMEM;
+    }
+    for (int u = 0; u < g; ++u)
+        for (int i = 0; i < kg; ++i) {
+            int v = nbr[(size_t)u * kg + i];
+            if (v >= 0 && v != u) {
+                adj[(size_t)u * g + v] = 1;
+                adj[(size_t)v * g + u] = 1;
+            }
+        }
+    for (int u = 0; u < g; ++u) {
+        double ux = l[2 * u], uy = l[2 * u + 1];
+        double fx = 0.0, fy = 0.0;
+        for (int v = 0; v < g; ++v) {
+            if (v == u)
+                continue;
+            double dx = (double)l[2 * v] - ux, dy = (double)l[2 * v + 1] - uy;
+            double r2 = dx * dx + dy * dy;
+            if (adj[(size_t)u * g + v]) {
+                double r = sqrt(r2);
+                if (r > 0.0) {
+                    double rest = scale * sqrt(sqdist(L + (size_t)u * d, L + (size_t)v * d, d));
+                    fx += (r - rest) * dx / r;
+                    fy += (r - rest) * dy / r;
+                }
+            }
+            fx -= repulsion * dx / (r2 + soft * soft);
+            fy -= repulsion * dy / (r2 + soft * soft);
+        }
+        double mx = step * fx, my = step * fy;
+        double len = sqrt(mx * mx + my * my);
+        if (len > max_move) {
+            mx *= max_move / len;
+            my *= max_move / len;
+        }
+        if (fixed && fixed[u])
+            mx = my = 0.0;
+        nl[2 * u] = ux + mx;
+        nl[2 * u + 1] = uy + my;
+    }
+    for (int e = 0; e < 2 * g; ++e)
+        l[e] = (float)nl[e];
+    free(adj); free(nl);
     return ORACLE_OK;
 }

@@ -1047,68 +1047,49 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         // landmark 0 and inserts +inf, which leaves its list unchanged.  Keeping
         // the insertion out of divergent control flow keeps the list in place
         // in registers.
-        auto walk = [&](auto rows_in_lds) {
-            constexpr bool IN_LDS = decltype(rows_in_lds)::value;
+        {
             unsigned long long mk = valid ? maskL[lane] : 0ull;
             const unsigned long long *row = reinterpret_cast<const unsigned long long *>(bitsL) + h * W * 32 + i32;
             int ntp = 0, ctp = 0;
             unsigned long long nb = 0ull, b = 0ull;
             next_word(mk, row, nb, ntp);
-            // the lane's next candidate position (0 and act = false when none is left)
-            auto advance = [&](int &j, bool &act) {
+            for (;;) {
                 if (b == 0ull && nb != 0ull) {
                     b = nb;
                     ctp = ntp;
                     next_word(mk, row, nb, ntp);
                 }
-                act = b != 0ull;
+                const bool act = b != 0ull;
+                if (__ballot(act) == 0ull) break;
                 const int bit = act ? __builtin_ctzll(b) : 0;
                 b &= b - 1ull;
                 // bit 32 h + pos of a word of tile pair ctp: position 64 ctp + 2 pos + h
-                j = act ? 64 * ctp + 2 * (bit & 31) + (bit >> 5) : 0;
-            };
-            int j;
-            bool act;
-            advance(j, act);
-            for (;;) {
-                if (__ballot(act) == 0ull) break;
-                int jn;
-                bool actn;
-                advance(jn, actn);
+                const int j = act ? 64 * ctp + 2 * (bit & 31) + (bit >> 5) : 0;
                 float acc = 0.f;
-                if constexpr (IN_LDS) {
+                // rows from the block's LDS copy or from global memory (separate
+                // code, so that each load has its own address space)
+                auto add_row = [&](const float4 lv, int q) {
+                    const float e0 = x[4 * q] - lv.x, e1 = x[4 * q + 1] - lv.y;
+                    const float e2 = x[4 * q + 2] - lv.z, e3 = x[4 * q + 3] - lv.w;
+                    acc = fmaf(e0, e0, acc);
+                    acc = fmaf(e1, e1, acc);
+                    acc = fmaf(e2, e2, acc);
+                    acc = fmaf(e3, e3, acc);
+                };
+                if constexpr (ROWS == 1) {
                     const float4 *Lr = reinterpret_cast<const float4 *>(rowsL + row_offset<RS>(j));
 #pragma unroll
-                    for (int q = 0; q < DP / 4; ++q) {
-                        const float4 lv = Lr[q];
-                        const float e0 = x[4 * q] - lv.x, e1 = x[4 * q + 1] - lv.y;
-                        const float e2 = x[4 * q + 2] - lv.z, e3 = x[4 * q + 3] - lv.w;
-                        acc = fmaf(e0, e0, acc);
-                        acc = fmaf(e1, e1, acc);
-                        acc = fmaf(e2, e2, acc);
-                        acc = fmaf(e3, e3, acc);
-                    }
+                    for (int q = 0; q < DP / 4; ++q) add_row(Lr[q], q);
                 } else {
                     const float4 *Lr = reinterpret_cast<const float4 *>(a.Lpad + (size_t)j * DP);
 #pragma unroll
-                    for (int q = 0; q < DP / 4; ++q) {
-                        const float4 lv = Lr[q];
-                        const float e0 = x[4 * q] - lv.x, e1 = x[4 * q + 1] - lv.y;
-                        const float e2 = x[4 * q + 2] - lv.z, e3 = x[4 * q + 3] - lv.w;
-                        acc = fmaf(e0, e0, acc);
-                        acc = fmaf(e1, e1, acc);
-                        acc = fmaf(e2, e2, acc);
-                        acc = fmaf(e3, e3, acc);
-                    }
+                    for (int q = 0; q < DP / 4; ++q) add_row(Lr[q], q);
                 }
                 // keys carry the landmark index (ties break on it), not the position
                 insert_sorted<KP>(sk, rej, act ? pack_key(acc, permL[j]) : (double)INFINITY);
                 m += act ? 1 : 0;
-                j = jn;
-                act = actn;
             }
-        };
-        walk(BoolTag<ROWS == 1>{});
+        }
         __builtin_amdgcn_wave_barrier();
 
         // k-th and (k+1)-th rescored distances

@@ -26,6 +26,8 @@ struct esom_ctx {
     size_t arena_bytes = 0;
     int64_t cap_n = 0;
     int cap_g = 0, cap_dp = 0, cap_pg = 0;
+    int64_t cap_mat = 0;
+    int cap_mat_k = 0;
     Scratch sc;
     // landmark-update workspace
     void *uws = nullptr;
@@ -35,6 +37,12 @@ struct esom_ctx {
     size_t som_xb_bytes = 0;
     int32_t *nearest = nullptr;
     int64_t nearest_cap = 0;
+    // 3-D projection: neighbour lists when the caller asks for none
+    int32_t *k3idx = nullptr;
+    size_t k3idx_bytes = 0;
+    // graph layout: the other position buffer of the synchronous steps
+    float *lay = nullptr;
+    size_t lay_bytes = 0;
     // optional per-kernel timing: pending event quadruples (prep, main, exact, end)
     bool timing = false;
     std::vector<hipEvent_t> pending;
@@ -87,7 +95,7 @@ void dev_free(esom_ctx *c, void *&p, size_t bytes) {
 namespace esom {
 // Lays the embed scratch out for (n, g, dp) capacities; the pair table holds
 // pg x pg entries (0 when no call so far needed it).
-size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg) {
+size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg, int64_t mat_n, int mat_k) {
     const int ntiles = ((g + TILE_PAIR - 1) / TILE_PAIR) * 2;
     char *p = static_cast<char *>(base);
     size_t off = 0;
@@ -111,19 +119,36 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg) {
     sc.fb_list = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     sc.fb_reason = static_cast<uint8_t *>(take((size_t)(n > 0 ? n : 1)));
     sc.fb_thresh = static_cast<float *>(take(sizeof(float) * (size_t)(n > 0 ? n : 1)));
+    sc.mat_cap = mat_n;
+    if (mat_n > 0) {
+        sc.mat_keys = static_cast<float *>(take(sizeof(float) * (size_t)mat_n * ntiles * TILE));
+        sc.mat_idx = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)mat_n * mat_k));
+        sc.mat_d2 = static_cast<float *>(take(sizeof(float) * (size_t)mat_n * mat_k));
+        sc.mat_mark = static_cast<uint8_t *>(take((size_t)mat_n));
+    } else {
+        sc.mat_keys = nullptr;
+        sc.mat_idx = nullptr;
+        sc.mat_d2 = nullptr;
+        sc.mat_mark = nullptr;
+    }
     return off;
 }
 }  // namespace esom
 
 namespace {
 
-int ensure_scratch(esom_ctx *c, int64_t n, int g, int dp, int pg, hipStream_t s) {
-    if (c->arena && n <= c->cap_n && g <= c->cap_g && dp <= c->cap_dp && pg <= c->cap_pg) return ESOM_OK;
+int ensure_scratch(esom_ctx *c, int64_t n, int g, int dp, int pg, hipStream_t s, int64_t mat_n = 0,
+                   int mat_k = 0) {
+    if (c->arena && n <= c->cap_n && g <= c->cap_g && dp <= c->cap_dp && pg <= c->cap_pg &&
+        (mat_n == 0 || (mat_n <= c->cap_mat && mat_k <= c->cap_mat_k)))
+        return ESOM_OK;
     int64_t nn = n > c->cap_n ? n + n / 4 : c->cap_n;
     int gg = g > c->cap_g ? g : c->cap_g;
     int dd = dp > c->cap_dp ? dp : c->cap_dp;
     int pp = pg > c->cap_pg ? pg : c->cap_pg;
-    const size_t bytes = carve(c->sc, nullptr, nn, gg, dd, pp);
+    int64_t mm = mat_n > c->cap_mat ? mat_n : c->cap_mat;
+    int mk = mat_k > c->cap_mat_k ? mat_k : c->cap_mat_k;
+    const size_t bytes = carve(c->sc, nullptr, nn, gg, dd, pp, mm, mk);
     if (c->arena) {
         hipError_t e = hipStreamSynchronize(s);
         if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
@@ -135,14 +160,18 @@ int ensure_scratch(esom_ctx *c, int64_t n, int g, int dp, int pg, hipStream_t s)
     int st = dev_alloc(c, &c->arena, bytes);
     if (st != ESOM_OK) {
         c->cap_n = c->cap_g = c->cap_dp = c->cap_pg = 0;
+        c->cap_mat = 0;
+        c->cap_mat_k = 0;
         return st;
     }
     c->arena_bytes = bytes;
-    carve(c->sc, c->arena, nn, gg, dd, pp);
+    carve(c->sc, c->arena, nn, gg, dd, pp, mm, mk);
     c->cap_n = nn;
     c->cap_g = gg;
     c->cap_dp = dd;
     c->cap_pg = pp;
+    c->cap_mat = mm;
+    c->cap_mat_k = mk;
     return ESOM_OK;
 }
 
@@ -166,6 +195,7 @@ int validate_common(const float *X, int64_t n, int32_t d, int64_t ldx, const flo
 struct Plan {
     int dp, dc, kp, C, jsel;
     bool fast;
+    bool mat;  // the materialised-distance path (d beyond the fused kernel's budget)
 };
 
 Plan make_plan(int d, int g, int k, int mode, int candidates) {
@@ -175,6 +205,7 @@ Plan make_plan(int d, int g, int k, int mode, int candidates) {
     p.kp = k <= 8 ? 8 : k <= 16 ? 16 : k <= 24 ? 24 : k <= 32 ? 32 : 0;
     const int maxdc = mode == 1 ? FAST_MAX_DC_BF16 : FAST_MAX_DC_FP32;
     p.fast = p.kp != 0 && p.dc <= maxdc && g <= FAST_MAX_G;
+    p.mat = !p.fast && p.kp != 0 && g <= FAST_MAX_G && p.dp <= ESOM_MAX_D;
     int C = candidates > 0 ? candidates : (mode == 1 ? 2 * k : k + 2);
     if (C < k + 1) C = k + 1;
     p.C = C;
@@ -193,7 +224,17 @@ namespace esom {
 bool embed_needs_pairs(int d, int g, const esom_params &P, int what) {
     const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
     // the pair table is read only by the fast kernels' projection
-    return what != EMBED_KNN_ONLY && pl.kp != 0 && (what == EMBED_PROJECT || pl.fast);
+    return what != EMBED_KNN_ONLY && pl.kp != 0 && (what == EMBED_PROJECT || pl.fast || pl.mat);
+}
+
+int64_t mat_chunk(int64_t n, int d, int g, const esom_params &P, int what) {
+    const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
+    if (!pl.mat || what != EMBED_FULL) return 0;
+    const int64_t gpad = ((g + TILE_PAIR - 1) / TILE_PAIR) * TILE_PAIR;
+    int64_t m = (int64_t)(MAT_KEY_BYTES / (sizeof(float) * (size_t)gpad));
+    m &= ~(int64_t)63;
+    if (m < 64) m = 64;
+    return n < m ? n : m;
 }
 
 int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t lds_per_block,
@@ -204,6 +245,11 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
     const int knn_only = what == EMBED_KNN_ONLY;
     const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
     const bool need_pairs = embed_needs_pairs(d, g, P, what);
+    // shapes beyond the fused kernel's register budget take the
+    // materialised-distance path when the scratch holds its buffers (the
+    // allocation-free entry point sends them to the exact path instead)
+    const bool use_mat = pl.mat && what == EMBED_FULL && sc.mat_cap > 0;
+    const int prep_mode = use_mat ? ESOM_MODE_FP32 : P.mode;  // FP32 keys on that path
     Prep &pr = sc.prep;
     pr.g = g;
     pr.d = d;
@@ -211,11 +257,12 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
     pr.dc = pl.dc;
     pr.ntiles = ((g + TILE_PAIR - 1) / TILE_PAIR) * 2;
     pr.npairs = pr.ntiles / 2;
-    pr.mode = P.mode;
+    pr.mode = prep_mode;
     pr.need_pairs = need_pairs ? 1 : 0;
     if (chunk <= 0 || chunk > n) chunk = n;
+    if (use_mat && chunk > sc.mat_cap) chunk = sc.mat_cap;
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipError_t e = launch_prep(pr, L, knn_only ? nullptr : l2d, P.mode, counters, knn_only ? 0 : (long long)n, s);
+    hipError_t e = launch_prep(pr, L, knn_only ? nullptr : l2d, prep_mode, counters, knn_only ? 0 : (long long)n, s);
     if (e != hipSuccess) return hip_fail(e, "landmark preparation launch");
     if (ev) (void)hipEventRecord(ev[1], s);
 
@@ -276,6 +323,41 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
             if (ev && last) (void)hipEventRecord(ev[2], s);
             e = launch_fallback(a, num_cus, lds_per_block, s);
             if (e != hipSuccess) return hip_fail(e, "exact-path launch");
+        } else if (use_mat) {
+            MatArgs mm;
+            mm.X = a.X;
+            mm.n = m;
+            mm.ldx = ldx;
+            mm.d = d;
+            mm.dp = pl.dp;
+            mm.g = g;
+            mm.ntiles = pr.ntiles;
+            mm.gpad = pr.ntiles * TILE;
+            mm.k = P.k;
+            mm.C = P.k + 2 < g ? P.k + 2 : g;
+            mm.exact_order = a.knn_exact_order;
+            mm.A = pr.A;
+            mm.norms = pr.norms;
+            mm.cent = pr.cent;
+            mm.Lpad = pr.Lpad;
+            mm.lmax = pr.lmax;
+            mm.perm = pr.perm;
+            mm.keys = sc.mat_keys;
+            mm.knn_idx = a.knn_idx ? a.knn_idx : sc.mat_idx;
+            mm.knn_d2 = a.knn_d2 ? a.knn_d2 : sc.mat_d2;
+            mm.knn_mark = a.knn_mark ? a.knn_mark : sc.mat_mark;
+            e = launch_materialise(mm, num_cus, s);
+            if (e != hipSuccess) return hip_fail(e, "materialised-distance launch");
+            // the projection from those neighbours; marked points go to the exact path
+            EmbedArgs ap = a;
+            ap.knn_idx = mm.knn_idx;
+            ap.knn_d2 = mm.knn_d2;
+            ap.knn_mark = mm.knn_mark;
+            e = launch_project(ap, pl.kp, num_cus, s);
+            if (e != hipSuccess) return hip_fail(e, "projection kernel launch");
+            if (ev && last) (void)hipEventRecord(ev[2], s);
+            e = launch_fallback(ap, num_cus, lds_per_block, s);
+            if (e != hipSuccess) return hip_fail(e, "exact-path launch");
         } else if (pl.fast) {
             e = launch_embed(a, P.mode, pl.kp, num_cus, lds_per_block, s);
             if (e != hipSuccess) return hip_fail(e, "embed kernel launch");
@@ -296,7 +378,9 @@ int run_embed(esom_ctx *c, const float *X, int64_t n, int d, int64_t ldx, const 
               const float *l2d, int g, const esom_params &P, float *out, int32_t *knn_idx,
               float *knn_d2, int what, hipStream_t s, uint8_t *knn_mark, int exact_order) {
     const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
-    int st = ensure_scratch(c, n, g, pl.dp, embed_needs_pairs(d, g, P, what) ? g : 0, s);
+    const int64_t mat_n = mat_chunk(n, d, g, P, what);
+    int st = ensure_scratch(c, n, g, pl.dp, embed_needs_pairs(d, g, P, what) ? g : 0, s, mat_n,
+                            mat_n ? P.k : 0);
     if (st != ESOM_OK) return st;
     hipEvent_t ev[4] = {nullptr, nullptr, nullptr, nullptr};
     const bool timed = c->timing && what != EMBED_KNN_ONLY;
@@ -326,11 +410,14 @@ void ctx_trim(esom_ctx *c) {
     dev_free(c, c->arena, c->arena_bytes);
     c->arena_bytes = 0;
     c->cap_n = c->cap_g = c->cap_dp = c->cap_pg = 0;
+    c->cap_mat = 0;
+    c->cap_mat_k = 0;
 }
 
-size_t embed_scratch_bytes(int64_t n, int g, int d) {
+size_t embed_scratch_bytes(int64_t n, int g, int d, const esom_params *P) {
     Scratch sc;
-    return carve(sc, nullptr, n, g, 16 * ((d + 15) / 16), g);
+    const int64_t mat_n = P ? mat_chunk(n, d, g, *P, EMBED_FULL) : 0;
+    return carve(sc, nullptr, n, g, 16 * ((d + 15) / 16), g, mat_n, mat_n ? P->k : 0);
 }
 
 int fail_msg(int code, const char *msg) { return fail(code, "%s", msg); }
@@ -505,6 +592,8 @@ void esom_destroy(esom_ctx *c) {
     dev_free(c, c->uws, c->uws_bytes);
     dev_free(c, reinterpret_cast<void *&>(c->som_xb), c->som_xb_bytes);
     dev_free(c, reinterpret_cast<void *&>(c->nearest), sizeof(int32_t) * (size_t)c->nearest_cap);
+    dev_free(c, reinterpret_cast<void *&>(c->k3idx), c->k3idx_bytes);
+    dev_free(c, reinterpret_cast<void *&>(c->lay), c->lay_bytes);
     dev_free(c, reinterpret_cast<void *&>(c->counters), sizeof(unsigned long long) * C_COUNT);
     delete c;
 }
@@ -760,6 +849,219 @@ int esom_landmark_update(esom_ctx *c, const float *X, int64_t n, int32_t d, int6
     u.counts = counts;
     e = launch_update(u, c->uws, c->num_cus, s);
     if (e != hipSuccess) return hip_fail(e, "landmark update launch");
+    return ESOM_OK;
+}
+
+int esom_embed3(esom_ctx *c, const float *X, int64_t n, int32_t d, int64_t ldx, const float *L_hd,
+                const float *L_3d, int32_t g, const esom_params *params, float *out, int32_t *knn_idx,
+                void *stream) {
+    t_err.clear();
+    if (!c) return fail(ESOM_EINVAL, "ctx is NULL");
+    if (!params) return fail(ESOM_EINVAL, "params is NULL");
+    const esom_params &P = *params;
+    int st = validate_common(X, n, d, ldx, L_hd, g);
+    if (st != ESOM_OK) return st;
+    st = validate_params(P, g);
+    if (st != ESOM_OK) return st;
+    if (!L_3d || !aligned4(L_3d)) return fail(ESOM_EINVAL, "L_3d is NULL or not 4-byte aligned");
+    if (n > 0 && (!out || !aligned4(out))) return fail(ESOM_EINVAL, "out is NULL or not 4-byte aligned");
+    if (knn_idx && !aligned4(knn_idx)) return fail(ESOM_EINVAL, "knn_idx must be 4-byte aligned");
+    if (n == 0) return ESOM_OK;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    int32_t *kidx = knn_idx;
+    if (!kidx) {
+        const size_t need = sizeof(int32_t) * (size_t)n * P.k;
+        if (need > c->k3idx_bytes) {
+            if (c->k3idx) {
+                e = hipStreamSynchronize(s);
+                if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+                dev_free(c, reinterpret_cast<void *&>(c->k3idx), c->k3idx_bytes);
+                c->k3idx_bytes = 0;
+            }
+            st = dev_alloc(c, reinterpret_cast<void **>(&c->k3idx), need);
+            if (st != ESOM_OK) return st;
+            c->k3idx_bytes = need;
+        }
+        kidx = c->k3idx;
+    }
+    // the k nearest landmarks (screen, exact selection, exact path)
+    st = run_embed(c, X, n, d, ldx, L_hd, nullptr, g, P, nullptr, kidx, nullptr, EMBED_KNN_ONLY, s,
+                   nullptr, knn_idx ? 1 : 0);
+    if (st != ESOM_OK) return st;
+    Embed3Args a;
+    a.X = X;
+    a.n = n;
+    a.ldx = ldx;
+    a.d = d;
+    a.g = g;
+    a.k = P.k;
+    a.use_cutoff = P.k < g ? 1 : 0;
+    a.L = L_hd;
+    a.l3 = L_3d;
+    a.knn_idx = kidx;
+    a.Wk = harmonic(P.k);
+    a.boost = P.boost;
+    a.cutoff = P.cutoff;
+    a.gravity = P.gravity;
+    a.adjust = P.adjust;
+    a.out = out;
+    e = launch_embed3(a, c->num_cus, s);
+    if (e != hipSuccess) return hip_fail(e, "3-D projection launch");
+    return ESOM_OK;
+}
+
+int esom_landmark_graph(const float *L_hd, int32_t g, int32_t d, int32_t kg, int32_t *nbr,
+                        float *dist2, void *stream) {
+    t_err.clear();
+    if (g < 2 || g > ESOM_MAX_G) return fail(ESOM_EINVAL, "g = %d outside [2, %d]", g, ESOM_MAX_G);
+    if (d < 1 || d > ESOM_MAX_D) return fail(ESOM_EINVAL, "d = %d outside [1, %d]", d, ESOM_MAX_D);
+    if (kg < 1 || kg > ESOM_GRAPH_MAX_K || kg > g - 1)
+        return fail(ESOM_EINVAL, "kg = %d outside [1, min(g - 1, %d)]", kg, ESOM_GRAPH_MAX_K);
+    if (!L_hd || !nbr || !aligned4(L_hd) || !aligned4(nbr) || (dist2 && !aligned4(dist2)))
+        return fail(ESOM_EINVAL, "NULL or misaligned array");
+    hipError_t e = launch_landmark_graph(L_hd, g, d, kg, nbr, dist2, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "landmark graph launch");
+    return ESOM_OK;
+}
+
+void esom_default_layout_params(esom_layout_params *p) {
+    if (!p) return;
+    p->scale = 1.0f;
+    p->repulsion = 0.05f;
+    p->softening = 0.5f;
+    p->step = 0.1f;
+    p->max_move = 0.5f;
+}
+
+int esom_graph_layout(esom_ctx *c, const float *L_hd, int32_t g, int32_t d, const int32_t *nbr, int32_t kg,
+                      float *L_2d, const uint8_t *fixed, int32_t steps, const esom_layout_params *lp,
+                      void *stream) {
+    t_err.clear();
+    if (!c || !lp) return fail(ESOM_EINVAL, "ctx or params is NULL");
+    if (g < 2 || g > ESOM_MAX_G) return fail(ESOM_EINVAL, "g = %d outside [2, %d]", g, ESOM_MAX_G);
+    if (d < 1 || d > ESOM_MAX_D) return fail(ESOM_EINVAL, "d = %d outside [1, %d]", d, ESOM_MAX_D);
+    if (kg < 1 || kg > ESOM_GRAPH_MAX_K) return fail(ESOM_EINVAL, "kg = %d outside [1, %d]", kg, ESOM_GRAPH_MAX_K);
+    if (steps < 0) return fail(ESOM_EINVAL, "steps = %d < 0", steps);
+    if (!L_hd || !nbr || !L_2d || !aligned4(L_hd) || !aligned4(nbr) || ((uintptr_t)L_2d & 7u))
+        return fail(ESOM_EINVAL, "NULL or misaligned array (L_2d needs 8-byte alignment)");
+    const bool ok = isfinite(lp->scale) && lp->scale >= 0.f && isfinite(lp->repulsion) && lp->repulsion >= 0.f &&
+                    isfinite(lp->softening) && lp->softening > 0.f && isfinite(lp->step) && lp->step >= 0.f &&
+                    isfinite(lp->max_move) && lp->max_move >= 0.f;
+    if (!ok) return fail(ESOM_EINVAL, "layout parameters must be finite and >= 0 (softening > 0)");
+    if (steps == 0) return ESOM_OK;
+    hipError_t e = hipSetDevice(c->device);
+    if (e != hipSuccess) return hip_fail(e, "hipSetDevice");
+    hipStream_t s = static_cast<hipStream_t>(stream);
+    const size_t need = sizeof(float) * 2 * (size_t)g;
+    if (need > c->lay_bytes) {
+        if (c->lay) {
+            e = hipStreamSynchronize(s);
+            if (e != hipSuccess) return hip_fail(e, "hipStreamSynchronize");
+            dev_free(c, reinterpret_cast<void *&>(c->lay), c->lay_bytes);
+            c->lay_bytes = 0;
+        }
+        int st = dev_alloc(c, reinterpret_cast<void **>(&c->lay), need);
+        if (st != ESOM_OK) return st;
+        c->lay_bytes = need;
+    }
+    // synchronous steps alternate between L_2d and the context's buffer; an
+    // odd count ends in the buffer and is copied back
+    float *bufs[2] = {L_2d, c->lay};
+    for (int t = 0; t < steps; ++t) {
+        e = launch_layout_step(L_hd, g, d, nbr, kg, bufs[t & 1], bufs[(t + 1) & 1], fixed, lp->scale,
+                               lp->repulsion, lp->softening, lp->step, lp->max_move, s);
+        if (e != hipSuccess) return hip_fail(e, "layout step launch");
+    }
+    if (steps & 1) {
+        e = hipMemcpyAsync(L_2d, c->lay, need, hipMemcpyDeviceToDevice, s);
+        if (e != hipSuccess) return hip_fail(e, "hipMemcpyAsync");
+    }
+    return ESOM_OK;
+}
+
+int esom_landmark_duplicate(float *L_hd, float *L_2d, int32_t g, int32_t d, int32_t j, float dx, float dy,
+                            void *stream) {
+    t_err.clear();
+    if (g < 1 || g >= ESOM_MAX_G) return fail(ESOM_EINVAL, "g = %d outside [1, %d)", g, ESOM_MAX_G);
+    if (d < 1 || d > ESOM_MAX_D) return fail(ESOM_EINVAL, "d = %d outside [1, %d]", d, ESOM_MAX_D);
+    if (j < 0 || j >= g) return fail(ESOM_EINVAL, "j = %d outside [0, g)", j);
+    if (!isfinite(dx) || !isfinite(dy)) return fail(ESOM_EINVAL, "offset must be finite");
+    if (!L_hd || !L_2d || !aligned4(L_hd) || !aligned4(L_2d)) return fail(ESOM_EINVAL, "NULL or misaligned array");
+    hipError_t e = launch_duplicate(L_hd, L_2d, g, d, j, dx, dy, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "duplicate launch");
+    return ESOM_OK;
+}
+
+int esom_landmark_remove(float *L_hd, float *L_2d, int32_t g, int32_t d, int32_t j, void *stream) {
+    t_err.clear();
+    if (g < 2 || g > ESOM_MAX_G) return fail(ESOM_EINVAL, "g = %d outside [2, %d]", g, ESOM_MAX_G);
+    if (d < 1 || d > ESOM_MAX_D) return fail(ESOM_EINVAL, "d = %d outside [1, %d]", d, ESOM_MAX_D);
+    if (j < 0 || j >= g) return fail(ESOM_EINVAL, "j = %d outside [0, g)", j);
+    if (!L_hd || !L_2d || !aligned4(L_hd) || !aligned4(L_2d)) return fail(ESOM_EINVAL, "NULL or misaligned array");
+    if (j == g - 1) return ESOM_OK;
+    hipError_t e = launch_remove(L_hd, L_2d, g, d, j, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "remove launch");
+    return ESOM_OK;
+}
+
+int esom_ablation_knn(int32_t algo, const float *X, int64_t n, int32_t d, const float *L_hd, int32_t g,
+                      int32_t k, int32_t *knn_idx, float *knn_dist2, void *stream) {
+    t_err.clear();
+    if (algo < 0 || algo > 3) return fail(ESOM_EINVAL, "algo = %d outside [0, 3]", algo);
+    if (n < 0 || n > (int64_t)INT32_MAX) return fail(ESOM_EINVAL, "n = %lld out of range", (long long)n);
+    if (d < 1 || d > ABL_MAX_D) return fail(ESOM_EINVAL, "d = %d outside [1, %d]", d, ABL_MAX_D);
+    if (g < 1 || g > ESOM_MAX_G) return fail(ESOM_EINVAL, "g = %d outside [1, %d]", g, ESOM_MAX_G);
+    if (k < 1 || k > ABL_MAX_K || k > g) return fail(ESOM_EINVAL, "k = %d outside [1, min(g, %d)]", k, ABL_MAX_K);
+    if (n == 0) return ESOM_OK;
+    if (!X || !L_hd || !knn_idx || !knn_dist2 || !aligned4(X) || !aligned4(L_hd) || !aligned4(knn_idx) ||
+        !aligned4(knn_dist2))
+        return fail(ESOM_EINVAL, "NULL or misaligned array");
+    hipError_t e = launch_ablation_knn(algo, X, n, d, L_hd, g, k, knn_idx, knn_dist2,
+                                       static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "ablation k-NN launch");
+    return ESOM_OK;
+}
+
+int esom_ablation_project(int32_t algo, const float *X, int64_t n, int32_t d, const float *L_hd,
+                          const float *L_2d, int32_t g, const esom_params *params, const int32_t *knn_idx,
+                          const float *knn_dist2, float *out, void *stream) {
+    t_err.clear();
+    if (!params) return fail(ESOM_EINVAL, "params is NULL");
+    const esom_params &P = *params;
+    if (algo < 0 || algo > 3) return fail(ESOM_EINVAL, "algo = %d outside [0, 3]", algo);
+    if (n < 0 || n > (int64_t)INT32_MAX) return fail(ESOM_EINVAL, "n = %lld out of range", (long long)n);
+    if (d < 1 || d > ABL_MAX_D) return fail(ESOM_EINVAL, "d = %d outside [1, %d]", d, ABL_MAX_D);
+    int st = validate_params(P, g);
+    if (st != ESOM_OK) return st;
+    if (P.k > ABL_MAX_K) return fail(ESOM_EINVAL, "k = %d above %d", P.k, ABL_MAX_K);
+    if (n == 0) return ESOM_OK;
+    if (!X || !L_hd || !L_2d || !knn_idx || !knn_dist2 || !out || !aligned4(X) || !aligned4(L_hd) ||
+        ((uintptr_t)L_2d & 7u) || !aligned4(knn_idx) || !aligned4(knn_dist2) || ((uintptr_t)out & 7u))
+        return fail(ESOM_EINVAL, "NULL or misaligned array");
+    int dev = 0, cus = 0;
+    hipError_t e = hipGetDevice(&dev);
+    if (e == hipSuccess) e = hipDeviceGetAttribute(&cus, hipDeviceAttributeMultiprocessorCount, dev);
+    if (e != hipSuccess) return hip_fail(e, "device query");
+    AbProjArgs a;
+    a.X = X;
+    a.L = L_hd;
+    a.l2d = L_2d;
+    a.idx = knn_idx;
+    a.d2 = knn_dist2;
+    a.n = n;
+    a.d = d;
+    a.g = g;
+    a.k = P.k;
+    a.boost = P.boost;
+    a.cutoff = P.cutoff;
+    a.gravity = P.gravity;
+    a.adjust = P.adjust;
+    a.Wk = (float)harmonic(P.k);
+    a.out = out;
+    e = launch_ablation_project(algo, a, cus, static_cast<hipStream_t>(stream));
+    if (e != hipSuccess) return hip_fail(e, "ablation projection launch");
     return ESOM_OK;
 }
 

@@ -65,6 +65,12 @@ struct Scratch {
     int32_t *fb_list = nullptr;     // fallback point list (cap_n)
     uint8_t *fb_reason = nullptr;   // per listed point reason flags (cap_n)
     float *fb_thresh = nullptr;     // per listed point: bound of its k-th distance^2 (cap_n)
+    // materialised-distance path, for one chunk of mat_cap points
+    int64_t mat_cap = 0;
+    float *mat_keys = nullptr;      // mat_cap x gpad
+    int32_t *mat_idx = nullptr;     // mat_cap x k
+    float *mat_d2 = nullptr;        // mat_cap x k
+    uint8_t *mat_mark = nullptr;    // mat_cap
     unsigned long long *counters = nullptr;  // C_COUNT
     Prep prep;
 };
@@ -133,6 +139,64 @@ struct UpdateArgs {
 size_t update_workspace_bytes(int64_t n, int g, int d);
 hipError_t launch_update(const UpdateArgs &u, void *ws, int num_cus, hipStream_t s);
 
+// The materialised-distance path (esom_materialise.hip): keys of a chunk of
+// points in device memory, then selection, exact rescoring and certificate.
+constexpr int MAT_MAX_C = 40;                    // candidates per point (k + 2, k <= 32)
+constexpr size_t MAT_KEY_BYTES = (size_t)256 << 20;  // keys of one chunk at most
+struct MatArgs {
+    const float *X;      // the chunk's rows (stride ldx)
+    int64_t n, ldx;      // points in the chunk
+    int d, dp, g, gpad, ntiles, k, C, exact_order;
+    const void *A;       // FP32 MFMA operand of the preparation (tile layout)
+    const float *norms, *cent, *Lpad, *lmax;
+    const int32_t *perm; // position -> landmark
+    float *keys;         // n x gpad
+    int32_t *knn_idx;    // n x k
+    float *knn_d2;       // n x k
+    uint8_t *knn_mark;   // n: 1 = the exact path decides this point
+};
+hipError_t launch_materialise(const MatArgs &m, int num_cus, hipStream_t s);
+
+// Projection into 3-D from given k nearest landmarks (esom_embed3.hip).
+struct Embed3Args {
+    const float *X;
+    int64_t n, ldx;
+    int d, g, k, use_cutoff;
+    const float *L, *l3;       // g x d, g x 3
+    const int32_t *knn_idx;    // n x k (any order; entries outside [0, g): NaN output)
+    double Wk;                 // the k-th harmonic number
+    double boost, cutoff, gravity, adjust;
+    float *out;                // n x 3
+};
+hipError_t launch_embed3(const Embed3Args &e, int num_cus, hipStream_t s);
+
+// The paper's kernel families as ablations (esom_ablation.hip).
+constexpr int ABL_MAX_K = 64;
+constexpr int ABL_MAX_D = 128;
+constexpr int ABL_LDS_FLOATS = 8192;  // landmark tile of the Shared k-NN kernel (32 KB)
+struct AbProjArgs {
+    const float *X, *L, *l2d;
+    const int32_t *idx;
+    const float *d2;
+    int64_t n;
+    int d, g, k;
+    float boost, cutoff, gravity, adjust, Wk;
+    float *out;
+};
+hipError_t launch_ablation_knn(int algo, const float *X, int64_t n, int d, const float *L, int g, int k,
+                               int32_t *idx, float *d2, hipStream_t s);
+hipError_t launch_ablation_project(int algo, const AbProjArgs &p, int num_cus, hipStream_t s);
+
+// Graph-mode supervision (esom_graph.hip).
+constexpr int GRAPH_MAX_K = 32;  // neighbours per landmark in the landmark graph
+hipError_t launch_landmark_graph(const float *L, int g, int d, int kg, int32_t *nbr, float *dist2,
+                                 hipStream_t s);
+hipError_t launch_layout_step(const float *L, int g, int d, const int32_t *nbr, int kg, const float *lin,
+                              float *lout, const uint8_t *fixed, double scale, double repulsion,
+                              double soft, double step, double max_move, hipStream_t s);
+hipError_t launch_duplicate(float *L, float *l2d, int g, int d, int j, float dx, float dy, hipStream_t s);
+hipError_t launch_remove(float *L, float *l2d, int g, int d, int j, hipStream_t s);
+
 // Online SOM training and the fit of added landmarks (esom_som.hip).
 hipError_t launch_som_gather(const float *X, int64_t n, int64_t ldx, int d, const int32_t *rows, int B,
                              float *Xb, hipStream_t s);
@@ -159,12 +223,17 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
 bool embed_needs_pairs(int d, int g, const esom_params &P, int what);
 // Lays out an embed scratch at base (NULL: only sizes it) for n points, g
 // landmarks, padded dimension dp and a pg x pg pair table; returns its bytes.
-size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg);
+size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg, int64_t mat_n = 0, int mat_k = 0);
+// Points per chunk of the materialised-distance path for this shape, or 0 when
+// the fused kernel (or the exact path) serves it.
+int64_t mat_chunk(int64_t n, int d, int g, const esom_params &P, int what);
 size_t ctx_held_bytes(const esom_ctx *c);
 // Device address of the context's embed scratch (changes when it grows).
 const void *ctx_arena(const esom_ctx *c);
 void ctx_trim(esom_ctx *c);
-size_t embed_scratch_bytes(int64_t n, int g, int d);
+// Bytes of an embed scratch for n points (with params: including the
+// materialised-distance path's buffers when that shape takes it).
+size_t embed_scratch_bytes(int64_t n, int g, int d, const esom_params *P = nullptr);
 int fail_msg(int code, const char *msg);
 // Checks the parameters of an embed over g landmarks (the esom_embed rules).
 int validate_params(const esom_params &P, int g);

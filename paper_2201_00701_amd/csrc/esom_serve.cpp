@@ -157,7 +157,7 @@ size_t slot_held(esom_server *S) {
 // Device bytes a request needs in a slot (beyond the resident datasets),
 // including the growth headroom the slot buffers are allocated with.
 size_t footprint(const Request &r) {
-    size_t b = embed_scratch_bytes(r.n + r.n / 4, r.g, r.d);
+    size_t b = embed_scratch_bytes(r.n + r.n / 4, r.g, r.d, &r.P);
     size_t buf = sizeof(float) * ((size_t)r.g * r.d + 2 * (size_t)r.g + 2 * (size_t)r.n);
     if (!r.dataset) buf += sizeof(float) * (size_t)r.n * r.d;
     return b + buf + buf / 8 + 4096;

@@ -67,6 +67,12 @@ class esom_serve_stats(ctypes.Structure):
         return {n: getattr(self, n) for n, _ in self._fields_}
 
 
+class esom_layout_params(ctypes.Structure):
+    _fields_ = [("scale", ctypes.c_float), ("repulsion", ctypes.c_float),
+                ("softening", ctypes.c_float), ("step", ctypes.c_float),
+                ("max_move", ctypes.c_float)]
+
+
 class EsomError(RuntimeError):
     def __init__(self, code, msg):
         super().__init__("esom error %d: %s" % (code, msg))
@@ -109,6 +115,25 @@ def load(path: str = LIB_PATH):
     lib.esom_som_train.restype = ctypes.c_int
     lib.esom_fit_landmarks.argtypes = [_vp, _vp, _i32, _i32, _vp, _i32, _i32, _f32, _vp, _vp]
     lib.esom_fit_landmarks.restype = ctypes.c_int
+    lib.esom_embed3.argtypes = [_vp, _vp, _i64, _i32, _i64, _vp, _vp, _i32,
+                                ctypes.POINTER(esom_params), _vp, _vp, _vp]
+    lib.esom_embed3.restype = ctypes.c_int
+    lib.esom_landmark_graph.argtypes = [_vp, _i32, _i32, _i32, _vp, _vp, _vp]
+    lib.esom_landmark_graph.restype = ctypes.c_int
+    lib.esom_default_layout_params.argtypes = [ctypes.POINTER(esom_layout_params)]
+    lib.esom_default_layout_params.restype = None
+    lib.esom_graph_layout.argtypes = [_vp, _vp, _i32, _i32, _vp, _i32, _vp, _vp, _i32,
+                                      ctypes.POINTER(esom_layout_params), _vp]
+    lib.esom_graph_layout.restype = ctypes.c_int
+    lib.esom_landmark_duplicate.argtypes = [_vp, _vp, _i32, _i32, _i32, _f32, _f32, _vp]
+    lib.esom_landmark_duplicate.restype = ctypes.c_int
+    lib.esom_landmark_remove.argtypes = [_vp, _vp, _i32, _i32, _i32, _vp]
+    lib.esom_landmark_remove.restype = ctypes.c_int
+    lib.esom_ablation_knn.argtypes = [_i32, _vp, _i64, _i32, _vp, _i32, _i32, _vp, _vp, _vp]
+    lib.esom_ablation_knn.restype = ctypes.c_int
+    lib.esom_ablation_project.argtypes = [_i32, _vp, _i64, _i32, _vp, _vp, _i32,
+                                          ctypes.POINTER(esom_params), _vp, _vp, _vp, _vp]
+    lib.esom_ablation_project.restype = ctypes.c_int
     lib.esom_sync.argtypes = [_vp, _vp]
     lib.esom_sync.restype = ctypes.c_int
     lib.esom_get_stats.argtypes = [_vp, _vp, ctypes.POINTER(esom_stats), _i32]
@@ -204,6 +229,80 @@ def esom_som_train(ctx, X, n, d, ldx, L_hd, L_2d, g, batch_idx, batch, steps, si
 
 def esom_fit_landmarks(L_hd, L_2d, g, d, p_2d, m, kfit, sigma, L_new, stream=0) -> int:
     return load().esom_fit_landmarks(L_hd, L_2d, g, d, p_2d, m, kfit, sigma, L_new, stream or None)
+
+
+def esom_embed3(ctx, X, n, d, ldx, L_hd, L_3d, g, params, out, knn_idx=0, stream=0) -> int:
+    return load().esom_embed3(ctx, X, n, d, ldx, L_hd, L_3d, g, ctypes.byref(params), out,
+                              knn_idx or None, stream or None)
+
+
+def esom_landmark_graph(L_hd, g, d, kg, nbr, dist2=0, stream=0) -> int:
+    return load().esom_landmark_graph(L_hd, g, d, kg, nbr, dist2 or None, stream or None)
+
+
+def esom_default_layout_params(**over) -> esom_layout_params:
+    p = esom_layout_params()
+    load().esom_default_layout_params(ctypes.byref(p))
+    for k, v in over.items():
+        setattr(p, k, v)
+    return p
+
+
+def esom_graph_layout(ctx, L_hd, g, d, nbr, kg, L_2d, fixed, steps, params, stream=0) -> int:
+    return load().esom_graph_layout(ctx, L_hd, g, d, nbr, kg, L_2d, fixed or None, steps,
+                                    ctypes.byref(params), stream or None)
+
+
+def esom_landmark_duplicate(L_hd, L_2d, g, d, j, dx=0.0, dy=0.0, stream=0) -> int:
+    return load().esom_landmark_duplicate(L_hd, L_2d, g, d, j, dx, dy, stream or None)
+
+
+def esom_landmark_remove(L_hd, L_2d, g, d, j, stream=0) -> int:
+    return load().esom_landmark_remove(L_hd, L_2d, g, d, j, stream or None)
+
+
+ABL_KNN = {"base": 0, "shared": 1, "gridinsert": 2, "bitonic": 3}
+ABL_PROJ = {"base": 0, "shared": 1, "aligned": 2, "registers": 3}
+
+
+def esom_ablation_knn(algo, X, n, d, L_hd, g, k, knn_idx, knn_dist2, stream=0) -> int:
+    return load().esom_ablation_knn(algo, X, n, d, L_hd, g, k, knn_idx, knn_dist2, stream or None)
+
+
+def esom_ablation_project(algo, X, n, d, L_hd, L_2d, g, params, knn_idx, knn_dist2, out,
+                          stream=0) -> int:
+    return load().esom_ablation_project(algo, X, n, d, L_hd, L_2d, g, ctypes.byref(params), knn_idx,
+                                        knn_dist2, out, stream or None)
+
+
+def ablation_knn(algo, X, L, k, stream=None):
+    """(idx n x k int32, dist2 n x k float32) from the named ablation kernel."""
+    import torch
+    X = _dev_f32(X, "X").contiguous()
+    L = _dev_f32(L, "L", X.shape[1]).contiguous()
+    n, d = X.shape
+    idx = torch.empty((n, k), dtype=torch.int32, device=X.device)
+    d2 = torch.empty((n, k), dtype=torch.float32, device=X.device)
+    _check(esom_ablation_knn(ABL_KNN[algo], X.data_ptr(), n, d, L.data_ptr(), L.shape[0], k,
+                             idx.data_ptr(), d2.data_ptr(), Context._stream(stream)))
+    return idx, d2
+
+
+def ablation_project(algo, X, L, l, idx, d2, out=None, stream=None, **params):
+    """Projection (n x 2) from given neighbours with the named ablation kernel."""
+    import torch
+    X = _dev_f32(X, "X").contiguous()
+    L = _dev_f32(L, "L", X.shape[1]).contiguous()
+    l = _dev_f32(l, "l", 2).contiguous()
+    n, d = X.shape
+    k = idx.shape[1]
+    if out is None:
+        out = torch.empty((n, 2), dtype=torch.float32, device=X.device)
+    p = esom_default_params(k=k, **params)
+    _check(esom_ablation_project(ABL_PROJ[algo], X.data_ptr(), n, d, L.data_ptr(), l.data_ptr(),
+                                 L.shape[0], p, idx.data_ptr(), d2.data_ptr(), out.data_ptr(),
+                                 Context._stream(stream)))
+    return out
 
 
 def esom_sync(ctx, stream=0) -> int:
@@ -335,6 +434,41 @@ class Context:
                               L.data_ptr(), l.data_ptr(), L.shape[0], batch_idx.data_ptr(), batch,
                               steps, sigma, alpha, fz, self._stream(stream)))
 
+    def embed3(self, X, L, l3, k=16, mode="fp32", boost=1.0, adjust=1.0, cutoff=10.0,
+               gravity=1e-5, candidates=0, knn=False, stream=None):
+        """3-D projection: returns out (n x 3), or (out, knn_idx n x k) with knn=True."""
+        import torch
+        X = _dev_f32(X, "X")
+        L = _dev_f32(L, "L", X.shape[1]).contiguous()
+        l3 = _dev_f32(l3, "l3", 3).contiguous()
+        n, d = X.shape
+        out = torch.empty((n, 3), dtype=torch.float32, device=X.device)
+        idx = torch.empty((n, k), dtype=torch.int32, device=X.device) if knn else None
+        p = esom_default_params(k=k, boost=boost, adjust=adjust, cutoff=cutoff, gravity=gravity,
+                                mode=mode, candidates=candidates)
+        _check(esom_embed3(self.handle, X.data_ptr(), n, d, X.stride(0), L.data_ptr(),
+                           l3.data_ptr(), L.shape[0], p, out.data_ptr(),
+                           idx.data_ptr() if knn else 0, self._stream(stream)))
+        return (out, idx) if knn else out
+
+    def graph_layout(self, L, nbr, l, steps=1, fixed=None, stream=None, **params):
+        """Runs layout steps on l (g x 2 float32 device tensor, in place)."""
+        import torch
+        L = _dev_f32(L, "L").contiguous()
+        l = _dev_f32(l, "l", 2)
+        if not l.is_contiguous():
+            raise ValueError("l must be contiguous (it is updated in place)")
+        if nbr.dtype != torch.int32 or nbr.dim() != 2 or not nbr.is_contiguous():
+            raise TypeError("nbr must be a contiguous g x kg int32 tensor")
+        fz = 0
+        if fixed is not None:
+            if fixed.dtype != torch.uint8 or fixed.numel() != L.shape[0] or not fixed.is_contiguous():
+                raise TypeError("fixed must be a contiguous uint8 tensor of g entries")
+            fz = fixed.data_ptr()
+        p = esom_default_layout_params(**params)
+        _check(esom_graph_layout(self.handle, L.data_ptr(), L.shape[0], L.shape[1], nbr.data_ptr(),
+                                 nbr.shape[1], l.data_ptr(), fz, steps, p, self._stream(stream)))
+
     def set_timing(self, enable=True):
         _check(esom_set_timing(self.handle, enable))
 
@@ -355,6 +489,19 @@ class Context:
                                    rsn.ctypes.data, n)
         _check(rc)
         return pts[:min(n, n2)], rsn[:min(n, n2)]
+
+
+def landmark_graph(L, kg, stream=None):
+    """(nbr g x kg int32, dist2 g x kg float32) device tensors: the kg nearest other
+    landmarks of every landmark (see esom_landmark_graph)."""
+    import torch
+    L = _dev_f32(L, "L").contiguous()
+    g, d = L.shape
+    nbr = torch.empty((g, kg), dtype=torch.int32, device=L.device)
+    dist = torch.empty((g, kg), dtype=torch.float32, device=L.device)
+    _check(esom_landmark_graph(L.data_ptr(), g, d, kg, nbr.data_ptr(), dist.data_ptr(),
+                               Context._stream(stream)))
+    return nbr, dist
 
 
 def fit_landmarks(L, l, p, kfit=8, sigma=1.0, stream=None):

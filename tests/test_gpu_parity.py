@@ -205,7 +205,7 @@ EDGE = [
     ("k32", 600, 16, 300, 32, "bf16", {}),
     ("k40_slowpath", 300, 16, 200, 40, "fp32", {}),
     ("d100_bf16", 400, 100, 128, 16, "bf16", {}),
-    ("d100_fp32_slowpath", 300, 100, 128, 16, "fp32", {}),
+    ("d100_fp32_materialised", 300, 100, 128, 16, "fp32", {}),
     ("g2000", 500, 16, 2000, 16, "bf16", {}),
     ("g4096_max_fast_bf16", 300, 8, 4096, 16, "bf16", {}),   # 64 tile pairs: every mask bit
     ("g4096_max_fast_fp32", 300, 8, 4096, 16, "fp32", {}),
@@ -228,6 +228,31 @@ def test_edge_cases(torch_dev, ctx, oracle_mod, label, n, d, g, k, mode, extra):
     ref = oracle_mod.embed(X, L, l, k, threads=8, **ox)
     span = float(max(np.ptp(l[:, 0]), np.ptp(l[:, 1])))
     check_parity(X, L, l, k, out, idx, ref, span, "edge/" + label)
+
+
+# The materialised-distance path: dimensions beyond the fused kernel's
+# register budget (d > 64 in FP32 mode, d > 128 in BF16 mode); the keys of a
+# chunk of points go through device memory.  Besides parity, the points must
+# not go whole to the exact path (n_slowpath == 0) and only a few per call.
+MAT = [("d100_fp32", 20000, 100, 400, 16, "fp32"), ("d200_bf16_k20", 5000, 200, 1024, 20, "bf16"),
+       ("d256_fp32_k8", 3001, 256, 300, 8, "fp32"), ("d70_fp32_ragged", 777, 70, 100, 16, "fp32"),
+       ("d80_fp32_k_eq_g", 500, 80, 30, 30, "fp32"),
+       ("d130_bf16_g4096_chunks", 40000, 130, 4096, 32, "bf16")]
+
+
+@pytest.mark.parametrize("label,n,d,g,k,mode", MAT, ids=[m[0] for m in MAT])
+def test_materialised_path(torch_dev, ctx, oracle_mod, label, n, d, g, k, mode):
+    X, L, l = _problem(_seed(label), n, d, g)
+    _say("case materialised %s n=%d d=%d g=%d k=%d mode=%s" % (label, n, d, g, k, mode))
+    ctx.stats(reset=True)
+    out, idx, _ = run_case(torch_dev, ctx, X, L, l, k, mode)
+    st = ctx.stats(reset=True)
+    _say("  stats %s" % st)
+    assert st["n_slowpath"] == 0
+    assert st["n_fallback"] <= max(16, n // 20)
+    ref = oracle_mod.embed(X, L, l, k, threads=8)
+    span = float(max(np.ptp(l[:, 0]), np.ptp(l[:, 1])))
+    check_parity(X, L, l, k, out, idx, ref, span, "materialised/" + label)
 
 
 def test_strided_rows(torch_dev, ctx, oracle_mod):

@@ -652,3 +652,191 @@ def test_fit_interpolates_three_neighbours_and_collinear_falls_back(oracle_mod):
     # far from every landmark with a small sigma: still finite (no weight underflows)
     far = oracle_mod.fit_landmarks(L, l, np.array([[500.0, -300.0]], np.float32), kfit=5, sigma=0.1)
     assert np.all(np.isfinite(far))
+
+
+# ---------------------------------------------------------------- 3-D output
+
+def _similarity_problem3(rng, g=24, d=7):
+    """L_j = c Q l_j + t with Q a d x 3 matrix of signed unit columns on distinct
+    axes and dyadic 3-D positions, so float32 stores every value exactly."""
+    l = rng.integers(-4, 5, size=(g, 3)).astype(np.float64) + rng.integers(0, 4, size=(g, 3)) / 4.0
+    perm = rng.permutation(d)
+    Q = np.zeros((d, 3))
+    for a in range(3):
+        Q[perm[a], a] = rng.choice([-1, 1])
+    c = 2.0
+    t = rng.integers(-5, 6, size=d).astype(np.float64)
+    return c * l @ Q.T + t, l, Q, c, t
+
+
+@pytest.mark.parametrize("seed", range(4))
+@pytest.mark.parametrize("k", [4, 6, 9])
+def test_embed3_exact_recovery_similarity(oracle_mod, seed, k):
+    # every segment coordinate of x = c Q p* + t + noise (noise orthogonal to Q)
+    # equals its 3-D counterpart at p*, so the objective is zero at p*
+    rng = np.random.default_rng(300 + seed)
+    L, l, Q, c, t = _similarity_problem3(rng)
+    n, d = 25, L.shape[1]
+    P = rng.integers(-12, 13, size=(n, 3)) / 4.0
+    noise = rng.integers(-3, 4, size=(n, d)) / 2.0
+    noise -= (noise @ Q) @ Q.T
+    X = c * P @ Q.T + t + noise
+    X32, L32, l32 = X.astype(np.float32), L.astype(np.float32), l.astype(np.float32)
+    assert np.array_equal(X32.astype(np.float64), X)
+    r = oracle_mod.embed3(X32, L32, l32, k, gravity=0.0)
+    err = np.abs(r["out"] - P).max(axis=1)
+    # k = 4 leaves three active neighbours: a plane's worth of pairs, which may
+    # not fix all three coordinates; larger k must recover p* exactly
+    if k > 4:
+        assert np.all(err < 1e-10), err.max()
+    # points on landmarks map to their 3-D positions
+    r2 = oracle_mod.embed3(L32, L32, l32, 7, gravity=0.0)
+    np.testing.assert_allclose(r2["out"], l, atol=1e-10)
+
+
+def test_embed3_planar_positions_reduce_to_2d(oracle_mod):
+    # with every 3-D position in the plane z = 0 the third coordinate decouples
+    # (no pair has a z component, gravity pulls z to 0) and x, y solve the 2-D system
+    rng = np.random.default_rng(17)
+    X, L, l = _random_problem(rng, n=80, d=6, g=30)
+    l3 = np.concatenate([l, np.zeros((len(l), 1), np.float32)], axis=1)
+    for k in (4, 8, 30):
+        r2 = oracle_mod.embed(X, L, l, k)
+        r3 = oracle_mod.embed3(X, L, l3, k)
+        assert r2["n_degenerate"] == 0 and r3["n_degenerate"] == 0
+        np.testing.assert_allclose(r3["out"][:, :2], r2["out"], rtol=1e-11, atol=1e-11)
+        assert np.all(r3["out"][:, 2] == 0.0)
+
+
+def _lstsq_reference3(X, L, l3, k, idx, s, adjust, gravity):
+    X = X.astype(np.float64); L = L.astype(np.float64); l3 = l3.astype(np.float64)
+    out = np.zeros((len(X), 3))
+    for i in range(len(X)):
+        A, b = [], []
+        for a_ in range(k):
+            for b_ in range(a_ + 1, k):
+                u, v = idx[i, a_], idx[i, b_]
+                H = L[v] - L[u]
+                h = l3[v] - l3[u]
+                if H @ H == 0 or h @ h == 0:
+                    continue
+                D = (X[i] - L[u]) @ H / (H @ H)
+                sw = np.sqrt(s[i, a_] * s[i, b_] * (h @ h) ** (1.0 - adjust))
+                A.append(sw * h / (h @ h))
+                b.append(sw * (D + h @ l3[u] / (h @ h)))
+        for a_ in range(k):
+            sg = np.sqrt(gravity * s[i, a_])
+            for c in range(3):
+                row = np.zeros(3)
+                row[c] = sg
+                A.append(row)
+                b.append(sg * l3[idx[i, a_], c])
+        out[i] = np.linalg.lstsq(np.array(A), np.array(b), rcond=None)[0]
+    return out
+
+
+@pytest.mark.parametrize("k,g,adjust", [(5, 16, 1.0), (8, 16, 0.5), (16, 16, 1.0), (7, 30, 1.4)])
+def test_embed3_normal_equations_match_lstsq(oracle_mod, k, g, adjust):
+    rng = np.random.default_rng(k * 31 + g)
+    X, L, l = _random_problem(rng, n=25, d=5, g=g)
+    l3 = np.concatenate([l, rng.normal(size=(g, 1)).astype(np.float32)], axis=1)
+    L[3] = L[1]   # duplicate HD landmark: its pair is skipped
+    l3[7] = l3[4]  # duplicate 3-D landmark
+    r = oracle_mod.embed3(X, L, l3, k, adjust=adjust, gravity=1e-3)
+    idx = r["idx"][:, :k]
+    s = np.stack([oracle_mod.scores(np.sqrt(r["d2"][i, :k]), g)[0] for i in range(len(X))])
+    ref = _lstsq_reference3(X, L, l3, k, idx, s, adjust, 1e-3)
+    np.testing.assert_allclose(r["out"], ref, rtol=1e-9, atol=1e-9)
+
+
+def test_embed3_rotation_and_translation_of_positions(oracle_mod):
+    # rotating / translating the 3-D positions rotates / translates the output
+    rng = np.random.default_rng(23)
+    X, L, l = _random_problem(rng, n=40, d=5, g=20)
+    l3 = np.concatenate([l, rng.normal(size=(20, 1)).astype(np.float32)], axis=1).astype(np.float64)
+    R, _ = np.linalg.qr(rng.normal(size=(3, 3)))
+    tau = np.array([0.5, -1.25, 2.0])
+    base = oracle_mod.embed3(X, L, l3.astype(np.float32), 7, gravity=0.0)["out"]
+    lr = (l3.astype(np.float32).astype(np.float64) @ R.T + tau).astype(np.float32)
+    moved = oracle_mod.embed3(X, L, lr, 7, gravity=0.0)["out"]
+    # float32 rounding of the rotated positions is the only difference
+    np.testing.assert_allclose(moved, base @ R.T + tau, atol=2e-4)
+
+
+# ---------------------------------------------------------------- graph-mode supervision
+
+@pytest.mark.parametrize("seed", range(3))
+def test_landmark_graph_matches_bruteforce(oracle_mod, seed):
+    rng = np.random.default_rng(400 + seed)
+    g, d, kg = 40, 3, 6
+    L = rng.integers(-3, 4, size=(g, d)).astype(np.float32)  # integer grid: exact ties
+    L[5] = L[9]  # an exact duplicate: distance 0 to each other
+    nbr, d2 = oracle_mod.landmark_graph(L, kg)
+    D = cdist(L.astype(np.float64), L.astype(np.float64), "sqeuclidean")
+    for u in range(g):
+        others = [v for v in range(g) if v != u]
+        order = sorted(others, key=lambda v: (D[u, v], v))[:kg]
+        assert list(nbr[u]) == order
+        np.testing.assert_array_equal(d2[u], D[u, order])
+    assert 9 in nbr[5] and 5 in nbr[9]
+
+
+def test_landmark_graph_more_slots_than_others(oracle_mod):
+    L = np.array([[0, 0], [1, 0], [0, 2]], np.float32)
+    nbr, d2 = oracle_mod.landmark_graph(L, 4)
+    assert list(nbr[0]) == [1, 2, -1, -1] and np.isinf(d2[0, 2:]).all()
+
+
+def test_layout_single_spring_reaches_rest_length(oracle_mod):
+    # two nodes on one edge, no repulsion: each moves step * (r - rest) toward
+    # the other, so with step 1/2 the new distance is exactly the rest length
+    L = np.array([[0, 0, 0], [3, 4, 0]], np.float32)         # |L_0 - L_1| = 5
+    l = np.array([[0, 0], [8, 0]], np.float32)               # r = 8
+    nbr = np.array([[1], [0]], np.int32)                     # the edge in both lists: once
+    out = oracle_mod.layout(L, nbr, l, steps=1, scale=0.4, repulsion=0.0, step=0.5, max_move=100)
+    # rest length 0.4 * 5 = 2: both move 3 toward each other
+    np.testing.assert_allclose(out, [[3, 0], [5, 0]], atol=1e-6)
+    # the edge in one list only acts the same way
+    out1 = oracle_mod.layout(L, np.array([[1], [-1]], np.int32), l, steps=1, scale=0.4,
+                             repulsion=0.0, step=0.5, max_move=100)
+    np.testing.assert_array_equal(out1, out)
+    # a spring at its rest length exerts nothing
+    rest = oracle_mod.layout(L, nbr, np.array([[0, 0], [2, 0]], np.float32), scale=0.4,
+                             repulsion=0.0, step=0.5)
+    np.testing.assert_array_equal(rest, [[0, 0], [2, 0]])
+
+
+def test_layout_repulsion_of_two_nodes(oracle_mod):
+    L = np.zeros((2, 2), np.float32)
+    l = np.array([[0, 0], [1.5, 0]], np.float32)
+    nbr = np.array([[-1], [-1]], np.int32)  # no edges
+    out = oracle_mod.layout(L, nbr, l, repulsion=0.8, soft=0.5, step=0.25, max_move=100)
+    push = 0.25 * 0.8 * 1.5 / (1.5 ** 2 + 0.25)
+    np.testing.assert_allclose(out, [[-push, 0], [1.5 + push, 0]], rtol=1e-6)
+    # the move is shortened to max_move
+    out2 = oracle_mod.layout(L, nbr, l, repulsion=0.8, soft=0.5, step=0.25, max_move=0.01)
+    np.testing.assert_allclose(out2, [[-0.01, 0], [1.51, 0]], rtol=1e-6)
+
+
+def test_layout_invariants(oracle_mod):
+    rng = np.random.default_rng(41)
+    g, d = 30, 5
+    L = rng.normal(size=(g, d)).astype(np.float32)
+    l = (rng.normal(size=(g, 2)) * 3).astype(np.float32)
+    nbr, _ = oracle_mod.landmark_graph(L, 4)
+    kw = dict(scale=0.7, repulsion=0.3, soft=0.2, step=0.05, max_move=1e9)
+    out = oracle_mod.layout(L, nbr, l, **kw).astype(np.float64)
+    # internal forces cancel in pairs: the centroid stays (no clamp, nothing fixed)
+    np.testing.assert_allclose(out.mean(axis=0), l.astype(np.float64).mean(axis=0), atol=1e-5)
+    # translation equivariance (integer shift: exact)
+    sh = np.array([3, -2], np.float32)
+    np.testing.assert_allclose(oracle_mod.layout(L, nbr, l + sh, **kw), out + sh, atol=1e-5)
+    # rotation equivariance (a quarter turn is exact)
+    rot = np.array([[0, -1], [1, 0]], np.float32)
+    np.testing.assert_allclose(oracle_mod.layout(L, nbr, l @ rot.T, **kw), out @ rot.T, atol=1e-5)
+    # fixed nodes keep their positions, the others still move
+    fixed = np.zeros(g, np.uint8)
+    fixed[[2, 7]] = 1
+    fo = oracle_mod.layout(L, nbr, l, fixed=fixed, **kw)
+    np.testing.assert_array_equal(fo[[2, 7]], l[[2, 7]])
+    assert np.all(np.abs(fo[0] - l[0]) > 0)

@@ -519,14 +519,16 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
     // t = D |h|^2 + h.l_i and D its segment coordinate.  Split as q D h plus
     // (q/|h|^2 h h^T) l_i, the second part sums over j into M_i l_i, so a pair
     // costs no dot product; s_i multiplies the sums of base i once.  The pair
-    // table supplies 1/(2|L_u - L_v|^2) and 1/|h|^2, both 0 for a skipped pair,
-    // so a skipped pair adds exactly 0.
+    // table supplies 1/(2|L_u - L_v|^2), 0 for coincident landmarks; 1/|h|^2
+    // comes from the 2-D difference at hand, and a pair with either length 0
+    // gets weight 0, so a skipped pair adds exactly 0.
     float pmax = 0.f;  // largest delta_j^2 / (2 |L_i - L_j|^2) over the pairs
     const bool unit_adjust = a.adjust == 1.0f;
     auto pair_term = [&](auto unit, float d2i, float lxi, float lyi, float d2j, float sj, float lxj,
-                         float lyj, float2 pv, float (&Mi)[3], float (&ri)[2]) {
-        const float inv = pv.x, ihh = pv.y;
+                         float lyj, float inv, float (&Mi)[3], float (&ri)[2]) {
         const float hx = lxj - lxi, hy = lyj - lyi;
+        const float hh = fmaf(hx, hx, hy * hy);
+        const float ihh = (inv > 0.f && hh > 0.f) ? __builtin_amdgcn_rcpf(hh) : 0.f;
         const float D = fmaf(d2i - d2j, inv, 0.5f);
         pmax = fmaxf(pmax, d2j * inv);
         float q;
@@ -562,16 +564,16 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
         // neighbour data in registers; each row of pair-table loads is issued
         // together, unconditionally (slots past k hold landmark 0, a valid
         // entry, and are never used), addressed by 32-bit byte offsets from
-        // the table base (g <= 4096: under 2^31 bytes)
+        // the table base (g <= 4096: under 2^26 bytes)
         const char *ptab = reinterpret_cast<const char *>(a.pairs);
 #pragma unroll
         for (int qi = 0; qi < KP - 1; ++qi) {
             if (qi < a.kact - 1) {
                 const unsigned rowoff = mul24(iposL[jq[qi]], (unsigned)a.g);
-                float2 pv[KP];
+                float pv[KP];
 #pragma unroll
                 for (int qj = qi + 1; qj < KP; ++qj)
-                    pv[qj] = *reinterpret_cast<const float2 *>(ptab + (size_t)((rowoff + iposL[jq[qj]]) * 8u));
+                    pv[qj] = *reinterpret_cast<const float *>(ptab + (size_t)((rowoff + iposL[jq[qj]]) * 4u));
                 float Mi[3] = {0.f, 0.f, 0.f}, ri[2] = {0.f, 0.f};
 #pragma unroll
                 for (int qj = qi + 1; qj < KP; ++qj)
@@ -608,7 +610,7 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
             const unsigned pu = iposL[ui];
             float Mi[3] = {0.f, 0.f, 0.f}, ri[2] = {0.f, 0.f};
             for (int qb = qi + 1; qb < a.kact; qb += 4) {
-                float2 pv[4];
+                float pv[4];
                 float d2j[4], sj[4], lxj[4], lyj[4];
 #pragma unroll
                 for (int u = 0; u < 4; ++u) {
@@ -616,7 +618,7 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
                     const bool ok = qj < a.kact;
                     const int vj = ok ? nbI[qj * 64 + lane] : 0;
                     const unsigned pw = iposL[vj];
-                    pv[u] = ok ? a.pairs[(size_t)min(pu, pw) * a.g + max(pu, pw)] : make_float2(0.f, 0.f);
+                    pv[u] = ok ? a.pairs[(size_t)min(pu, pw) * a.g + max(pu, pw)] : 0.f;
                     d2j[u] = ok ? nbD2[qj * 64 + lane] : 0.f;
                     sj[u] = ok ? nbS[qj * 64 + lane] : 0.f;
                     const float2 lv = reinterpret_cast<const float2 *>(a.l2d)[vj];

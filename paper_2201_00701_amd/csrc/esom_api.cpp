@@ -109,7 +109,7 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg, int64_t 
     sc.prep.A16 = take(sizeof(uint16_t) * (size_t)ntiles * TILE * dp);
     sc.prep.norms = static_cast<float *>(take(sizeof(float) * (size_t)ntiles * TILE));
     sc.prep.Lpad = static_cast<float *>(take(sizeof(float) * (size_t)g * dp));
-    sc.prep.pairs = pg > 0 ? static_cast<float2 *>(take(sizeof(float2) * (size_t)pg * pg)) : nullptr;
+    sc.prep.pairs = pg > 0 ? static_cast<float *>(take(sizeof(float) * (size_t)pg * pg)) : nullptr;
     sc.prep.lmax = static_cast<float *>(take(2 * sizeof(float)));
     sc.prep.perm = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
     sc.prep.ipos = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
@@ -262,7 +262,7 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
     if (chunk <= 0 || chunk > n) chunk = n;
     if (use_mat && chunk > sc.mat_cap) chunk = sc.mat_cap;
     if (ev) (void)hipEventRecord(ev[0], s);
-    hipError_t e = launch_prep(pr, L, knn_only ? nullptr : l2d, prep_mode, counters, knn_only ? 0 : (long long)n, s);
+    hipError_t e = launch_prep(pr, L, prep_mode, counters, knn_only ? 0 : (long long)n, s);
     if (e != hipSuccess) return hip_fail(e, "landmark preparation launch");
     if (ev) (void)hipEventRecord(ev[1], s);
 

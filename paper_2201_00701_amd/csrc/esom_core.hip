@@ -252,32 +252,29 @@ __device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict_
     }
 }
 
-// Pair table pairs[u][v] = (1 / (2 |L_u - L_v|^2), 1 / |l_v - l_u|^2): the
-// high-dimensional factor of the segment coordinate (Section 3, the
-// projection of a point onto the segment between two landmarks) and the
-// inverse squared 2-D segment length, both from FP64 differences and both 0
-// for a skipped pair; indexed by landmark positions.  Each entry depends only
-// on the two landmarks, so the per-point pair loop needs no division; the
-// table is exactly symmetric (the same FP64 sums either way).  A
-// 256-thread block computes a 16 x 16 tile of pairs from the two
-// 16-row slices of L staged in LDS (row stride d + 1 floats: no bank
-// conflicts between the 16 rows a wave reads); rows are read and the table
-// written coalesced.
+// Pair table pairs[u][v] = 1 / (2 |L_u - L_v|^2), the high-dimensional factor
+// of the segment coordinate (Section "Projection step": the projection of a
+// point onto the segment between two landmarks), from FP64 differences, 0
+// when the two landmarks coincide; indexed by landmark positions.  Each entry
+// depends only on the two landmarks, so the per-point pair loop needs no
+// division and the table serves any 2-D positions; it is exactly symmetric
+// (the same FP64 sums either way).  The 2-D factor 1 / |l_v - l_u|^2 is
+// formed in the pair loop instead: a second table entry made every pair's
+// load 8 bytes, and at 1024 landmarks the table (8 MB) no longer stayed in a
+// die's L2.  A 256-thread block computes a 16 x 16 tile of pairs from the two
+// 16-row slices of L staged in LDS (row stride d + 1 floats: no bank conflicts
+// between the 16 rows a wave reads); rows are read and the table written
+// coalesced.
 constexpr int PAIR_TILE = 16;
 
 __device__ __forceinline__ void prep_pairs(int blk, float *prs, const float *__restrict__ L,
-                                           const float *__restrict__ l2d, const int *__restrict__ perm,
-                                           int g, int d, float2 *__restrict__ pairs) {
-    // prs: 2 x PAIR_TILE x (d + 1) floats of LDS, then 2 x PAIR_TILE 2-D positions
+                                           const int *__restrict__ perm, int g, int d,
+                                           float *__restrict__ pairs) {
+    // prs: 2 x PAIR_TILE x (d + 1) floats of LDS
     const int ntu = (g + PAIR_TILE - 1) / PAIR_TILE;
     const int u0 = (blk / ntu) * PAIR_TILE, v0 = (blk % ntu) * PAIR_TILE;
     const int rs = d + 1;
     float *Lu = prs, *Lv = prs + PAIR_TILE * rs;
-    float2 *lu2 = reinterpret_cast<float2 *>(prs + 2 * PAIR_TILE * rs);  // 2 PAIR_TILE rs is even
-    if (l2d && threadIdx.x < 2 * PAIR_TILE) {
-        const int r = threadIdx.x % PAIR_TILE, w = (threadIdx.x < PAIR_TILE ? u0 : v0) + r;
-        lu2[threadIdx.x] = w < g ? reinterpret_cast<const float2 *>(l2d)[perm[w]] : make_float2(0.f, 0.f);
-    }
     for (int e = threadIdx.x; e < PAIR_TILE * d; e += blockDim.x) {
         const int r = e / d, q = e % d;
         Lu[r * rs + q] = u0 + r < g ? L[(size_t)perm[u0 + r] * d + q] : 0.f;
@@ -292,20 +289,8 @@ __device__ __forceinline__ void prep_pairs(int blk, float *prs, const float *__r
         const double df = (double)Lv[tx * rs + q] - (double)Lu[ty * rs + q];
         s = fma(df, df, s);
     }
-    // a pair is skipped (both entries 0) when its high-dimensional or its 2-D
-    // landmarks coincide; the 2-D part is absent for k-NN-only calls
-    float iv = 0.f, w = 0.f;
-    if (s > 0.0 && l2d) {
-        const float2 lu = lu2[ty], lv = lu2[PAIR_TILE + tx];
-        const double hx = (double)lv.x - (double)lu.x, hy = (double)lv.y - (double)lu.y;
-        const double hh = fma(hx, hx, hy * hy);
-        // FP32 reciprocals (about 1 ulp): the fast kernel uses both in FP32
-        if (hh > 0.0) {
-            iv = 0.5f * __builtin_amdgcn_rcpf((float)s);
-            w = __builtin_amdgcn_rcpf((float)hh);
-        }
-    }
-    pairs[(size_t)u * g + v] = make_float2(iv, w);
+    // FP32 reciprocal (about 1 ulp): the fast kernel uses it in FP32
+    pairs[(size_t)u * g + v] = s > 0.0 ? 0.5f * __builtin_amdgcn_rcpf((float)s) : 0.f;
 }
 
 // The landmark tables and the pair table in one launch: blocks 0 .. nlb-1
@@ -315,17 +300,16 @@ __global__ void __launch_bounds__(256) prep_tables(const float *__restrict__ L, 
                                                    const float *__restrict__ cent, void *__restrict__ A,
                                                    void *__restrict__ A16,
                                                    float *__restrict__ norms, float *__restrict__ Lpad,
-                                                   float *__restrict__ lmax, const float *__restrict__ l2d,
-                                                   float2 *__restrict__ pairs) {
+                                                   float *__restrict__ lmax, float *__restrict__ pairs) {
     extern __shared__ __align__(16) float prs[];
     if ((int)blockIdx.x < nlb)
         prep_landmarks((int)blockIdx.x, L, perm, g, gpad, d, dp, mode, cent, A, A16, norms, Lpad, lmax,
                        reinterpret_cast<unsigned *>(prs));
     else
-        prep_pairs((int)blockIdx.x - nlb, prs, L, l2d, perm, g, d, pairs);
+        prep_pairs((int)blockIdx.x - nlb, prs, L, perm, g, d, pairs);
 }
 
-hipError_t launch_prep(const Prep &P, const float *L, const float *l2d, int mode,
+hipError_t launch_prep(const Prep &P, const float *L, int mode,
                        unsigned long long *counters, long long n_points, hipStream_t s) {
     hipLaunchKernelGGL(prep_centroid, dim3(P.dp + (P.g + ASSIGN_PER_BLOCK - 1) / ASSIGN_PER_BLOCK),
                        dim3(256), sizeof(float) * P.d * 64, s, L, P.g, P.d, P.dp, P.cent, P.lmax, counters,
@@ -338,8 +322,8 @@ hipError_t launch_prep(const Prep &P, const float *L, const float *l2d, int mode
     const int nlb = (gpad + 3) / 4;
     const int ntu = P.need_pairs ? (P.g + PAIR_TILE - 1) / PAIR_TILE : 0;
     hipLaunchKernelGGL(prep_tables, dim3((unsigned)(nlb + ntu * ntu)), dim3(256),
-                       sizeof(float) * 2 * PAIR_TILE * (P.d + 1) + sizeof(float2) * 2 * PAIR_TILE, s, L, P.perm, P.g, gpad, P.d, P.dp, mode,
-                       nlb, P.cent, P.A, P.A16, P.norms, P.Lpad, P.lmax, l2d, P.pairs);
+                       sizeof(float) * 2 * PAIR_TILE * (P.d + 1), s, L, P.perm, P.g, gpad, P.d, P.dp, mode,
+                       nlb, P.cent, P.A, P.A16, P.norms, P.Lpad, P.lmax, P.pairs);
     return hipGetLastError();
 }
 

@@ -45,7 +45,7 @@ struct Prep {
     void *A16 = nullptr;     // FP32 mode: the same operand in BF16 (threshold pass); BF16 mode: unused
     float *norms = nullptr;  // ntiles * 32: |L_j - c|^2 in MFMA row order
     float *Lpad = nullptr;   // g * dp:  L rows padded with zeros to dp
-    float2 *pairs = nullptr;  // g * g (when need_pairs): (1 / (2 |L_u - L_v|^2), 1 / |l_v - l_u|^2), (0, 0) if skipped
+    float *pairs = nullptr;  // g * g (when need_pairs): 1 / (2 |L_u - L_v|^2), 0 for coincident landmarks
     float *lmax = nullptr;   // 2:       max_j |L_j - c|, max_j |BF16(-2 (L_j - c)) + 2 (L_j - c)|
     // Landmark order of the screen tiles, rows and pair table: position ->
     // landmark (perm) and landmark -> position (ipos).  Landmarks that are
@@ -82,7 +82,7 @@ struct EmbedArgs {
     const void *A;    // screen operand of the candidate pass (BF16 or FP32 by mode)
     const void *A16;  // BF16 operand of the threshold pass (== A in BF16 mode)
     const float *norms, *cent, *Lpad, *l2d, *lmax;
-    const float2 *pairs;
+    const float *pairs;
     const int32_t *perm, *ipos;  // position -> landmark, landmark -> position
     int k, kact, jsel;  // kact: neighbours with non-zero score; jsel: per-lane order statistic
     int use_cutoff;
@@ -112,7 +112,7 @@ struct EmbedArgs {
 };
 
 // Launchers (esom_core.hip).
-hipError_t launch_prep(const Prep &P, const float *L, const float *l2d, int mode, unsigned long long *counters,
+hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long long *counters,
                        long long n_points, hipStream_t s);
 hipError_t launch_embed(const EmbedArgs &a, int mode, int kp, int num_cus, size_t lds_per_block,
                         hipStream_t s);

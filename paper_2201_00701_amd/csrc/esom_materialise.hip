@@ -198,7 +198,7 @@ __global__ void __launch_bounds__(256) select_kernel(MatArgs m) {
         const float d2k1 = C > k ? cd[wv][k] : INFINITY;
         const float rb = (float)(m.dp + 3) * U32;  // rounding bound of a rescored distance
         bool mark = !(tau < INFINITY ? d2k * (1.f + rb) < rhs : d2k < INFINITY);
-        if (d2k1 - d2k <= 2.f * rb * d2k1) mark = true;  // k-th / (k+1)-th closer than FP32 orders
+        if (d2k1 < INFINITY && d2k1 - d2k <= 2.f * rb * d2k1) mark = true;  // k-th / (k+1)-th closer than FP32 orders
         // adjacent entries FP32 cannot order when the caller wants the exact order
         if (m.exact_order)
             for (int q = 1; q < k; ++q)

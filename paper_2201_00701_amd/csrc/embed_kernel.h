@@ -1,19 +1,23 @@
 // Fused EmbedSOM kernel for gfx950 (one wavefront = 64 points).
 //
 // Phase A, screen (MFMA).  The wave holds its 64 points as two 32-point MFMA
-// B operands (centred on the landmark centroid, BF16 or FP32) in registers
-// and streams 32-landmark A tiles (-2 (L_j - c), prepared once per landmark
-// set).  v_mfma_f32_32x32x* with C initialised to |L_j - c|^2 gives
+// B operands (centred on the landmark centroid) in registers and streams
+// 32-landmark A tiles (-2 (L_j - c), prepared once per landmark set).
+// v_mfma_f32_32x32x* with C initialised to |L_j - c|^2 gives
 //   key_ij = |L_j - c|^2 - 2 <x_i - c, L_j - c>  =  delta_ij^2 - |x_i - c|^2,
 // so keys rank the landmarks of a point exactly like the distances do.  In
 // the 32x32 output layout lane l holds 16 keys of point (l mod 32); the two
 // lanes l and l+32 of a point see disjoint halves of every tile.
-//   Pass 1 keeps, per lane, the minimum key of 32 landmark groups (register
-//   slot x tile parity).  A lane's j-th smallest group minimum bounds from
-//   above j distinct keys of its half, so with j = ceil(C/2) the larger of the
-//   two lanes' values, tau, has at least C keys at or below it.
-//   Pass 2 recomputes the keys and shifts one bit per key (key <= tau) into a
-//   per-lane bitmap in LDS: the candidate set, with no capacity limit.
+//   Pass 1 (BF16 operands) keeps, per lane, the minimum key of 32 landmark
+//   groups (register slot x tile parity).  A lane's j-th smallest group
+//   minimum bounds from above j distinct keys of its half, so with
+//   j = ceil(C/2) the larger of the two lanes' values has at least C keys at
+//   or below it; widened by both passes' error bounds it is the threshold tau.
+//   Pass 2 recomputes the keys more accurately (FP32 operands in FP32 mode;
+//   in BF16 mode both operands split into high and low BF16 parts, three
+//   products per element, which leaves an error near 2^-16 of the products
+//   instead of 2^-8) and shifts one bit per key (key <= tau) into a per-lane
+//   bitmap in LDS: the candidate set, with no capacity limit.
 // Phase B, exact selection (one lane = one point).  Every candidate is
 // rescored with exact FP32 differences and inserted into a sorted register
 // list; keys are doubles packing (delta^2, landmark index) so a plain
@@ -305,6 +309,31 @@ __host__ __device__ inline int wave_smem_bytes(int kp, int k, int npair_tiles) {
     return (bits > nbr ? bits : nbr) + 512 + 1024;
 }
 
+// Centred values x_t - c_t of dimensions 16 c + 8 h + e (e < 8) of the point
+// row xr; zero past d and for an invalid point.
+__device__ __forceinline__ void centred8(const EmbedArgs &a, const float *xr, const float *centL, int c, int h,
+                                         bool valid, float (&v)[8]) {
+    if (a.x_vec4) {
+        const float4 *x4 = reinterpret_cast<const float4 *>(xr + 16 * c + 8 * h);
+        const float4 *c4 = reinterpret_cast<const float4 *>(centL + 16 * c + 8 * h);
+#pragma unroll
+        for (int u = 0; u < 2; ++u) {
+            const float4 q = valid ? x4[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+            const float4 cv = valid ? c4[u] : make_float4(0.f, 0.f, 0.f, 0.f);
+            v[4 * u] = q.x - cv.x;
+            v[4 * u + 1] = q.y - cv.y;
+            v[4 * u + 2] = q.z - cv.z;
+            v[4 * u + 3] = q.w - cv.w;
+        }
+    } else {
+#pragma unroll
+        for (int e = 0; e < 8; ++e) {
+            const int d0 = 16 * c + 8 * h + e;
+            v[e] = (valid && d0 < a.d) ? xr[d0] - centL[d0] : 0.f;
+        }
+    }
+}
+
 template <int MODE, int DC>
 struct PointOperand;
 
@@ -376,6 +405,47 @@ __device__ __forceinline__ void screen_tile(const float *Nbase, int t, int lane,
             acc[0] = __builtin_amdgcn_mfma_f32_32x32x2f32(T.a[s], P.b[0][s], acc[0], 0, 0, 0);
             acc[1] = __builtin_amdgcn_mfma_f32_32x32x2f32(T.a[s], P.b[1][s], acc[1], 0, 0, 0);
         }
+    }
+}
+
+// Split BF16 keys of tile t: acc[p] = |L|^2 + Al B_p + Ah Bl_p + Ah B_p (the
+// small terms first), with A = Ah + Al and B = B_p + Bl_p the high and low
+// BF16 parts of the two operands.
+template <int DC>
+__device__ __forceinline__ void screen_tile_split(const float *Nbase, int t, int lane, const TileRegs<1, DC> &Th,
+                                                  const TileRegs<1, DC> &Tl, const PointOperand<1, DC> &P,
+                                                  const PointOperand<1, DC> &Pl, f32x16 (&acc)[2]) {
+    f32x16 nrm;
+    {
+        const float4 *np = reinterpret_cast<const float4 *>(Nbase + (size_t)(t * 2 + (lane >> 5)) * 16);
+#pragma unroll
+        for (int i = 0; i < 4; ++i) {
+            const float4 n = np[i];
+            nrm[4 * i] = n.x;
+            nrm[4 * i + 1] = n.y;
+            nrm[4 * i + 2] = n.z;
+            nrm[4 * i + 3] = n.w;
+        }
+    }
+    acc[0] = nrm;
+    acc[1] = nrm;
+#pragma unroll
+    for (int c = 0; c < DC; ++c) {
+        const bf16x8 al = __builtin_bit_cast(bf16x8, Tl.a[c]);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, P.b[0][c], acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, P.b[1][c], acc[1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < DC; ++c) {
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, Th.a[c]);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Pl.b[0][c], acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, Pl.b[1][c], acc[1], 0, 0, 0);
+    }
+#pragma unroll
+    for (int c = 0; c < DC; ++c) {
+        const bf16x8 ah = __builtin_bit_cast(bf16x8, Th.a[c]);
+        acc[0] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, P.b[0][c], acc[0], 0, 0, 0);
+        acc[1] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, P.b[1][c], acc[1], 0, 0, 0);
     }
 }
 
@@ -796,7 +866,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         // ---------------- point operands (centred), and |x - c|^2.  Pass 1
         // always runs on the BF16 operand; FP32 mode builds its FP32 operand
         // for pass 2 afterwards.
-        PointOperand<1, DC> P16;
+        PointOperand<1, DC> P16, P16lo;  // P16lo: BF16 mode's pass 2
         float xnp[2], dxp[2];  // |x - c|^2 and |bf16(x - c) - (x - c)|^2
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
@@ -806,31 +876,16 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             float part = 0.f, dpart = 0.f;
 #pragma unroll
             for (int c = 0; c < DC; ++c) {
+                float v[8];
+                centred8(a, xr, centL, c, h, valid, v);
                 unsigned w[4];
-                float4 xv[2] = {make_float4(0.f, 0.f, 0.f, 0.f), make_float4(0.f, 0.f, 0.f, 0.f)};
-                if (a.x_vec4 && valid) {
-                    const float4 *x4 = reinterpret_cast<const float4 *>(xr + 16 * c + 8 * h);
-                    const float4 *c4 = reinterpret_cast<const float4 *>(centL + 16 * c + 8 * h);
-#pragma unroll
-                    for (int u = 0; u < 2; ++u) {
-                        const float4 q = x4[u], cv = c4[u];
-                        xv[u] = make_float4(q.x - cv.x, q.y - cv.y, q.z - cv.z, q.w - cv.w);
-                    }
-                }
 #pragma unroll
                 for (int e = 0; e < 8; e += 2) {
-                    const int d0 = 16 * c + 8 * h + e;
-                    const float4 &xq = xv[e >> 2];
-                    float v0 = (e & 2) ? xq.z : xq.x, v1 = (e & 2) ? xq.w : xq.y;
-                    if (!a.x_vec4) {
-                        v0 = (valid && d0 < a.d) ? xr[d0] - centL[d0] : 0.f;
-                        v1 = (valid && d0 + 1 < a.d) ? xr[d0 + 1] - centL[d0 + 1] : 0.f;
-                    }
-                    part = fmaf(v0, v0, part);
-                    part = fmaf(v1, v1, part);
-                    const unsigned b0 = bf16_bits_rne(v0), b1 = bf16_bits_rne(v1);
+                    part = fmaf(v[e], v[e], part);
+                    part = fmaf(v[e + 1], v[e + 1], part);
+                    const unsigned b0 = bf16_bits_rne(v[e]), b1 = bf16_bits_rne(v[e + 1]);
                     // quantisation errors (exact in FP32)
-                    const float q0 = __uint_as_float(b0 << 16) - v0, q1 = __uint_as_float(b1 << 16) - v1;
+                    const float q0 = __uint_as_float(b0 << 16) - v[e], q1 = __uint_as_float(b1 << 16) - v[e + 1];
                     dpart = fmaf(q0, q0, dpart);
                     dpart = fmaf(q1, q1, dpart);
                     w[e >> 1] = b0 | (b1 << 16);
@@ -848,7 +903,8 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         // preparation); plus FP32 accumulation and centring, (2 d_pad + 16) u
         // (|x'| + max|L - c|)^2.  FP32 operands are exact and 2 (2u + u^2) |x'|
         // max|L - c| bounds their products.  The FP32 evaluation of the bound
-        // is covered by the factor 1.01.
+        // is covered by the factor 1.01.  (The split BF16 keys of pass 2 have
+        // their own bound, e2 below.)
         float e16[2], e32[2];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
@@ -894,6 +950,24 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 store(tp);
             }
         };
+        // BF16 mode's pass 2: split operands, high parts from LDS or global
+        // memory, low parts from global memory (a.A16)
+        auto screen_pass_split = [&](auto in_lds, auto consume, auto store) {
+            const void *Ab = decltype(in_lds)::value ? static_cast<const void *>(tilesL) : a.A;
+            const float *Nb = decltype(in_lds)::value ? normsL : a.norms;
+            TileRegs<1, DC> Th, Tl;
+            for (int tp = 0; tp < W; ++tp) {
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    f32x16 acc[2];
+                    load_tile<1, DC>(Ab, 2 * tp + half, lane, Th);
+                    load_tile<1, DC>(a.A16, 2 * tp + half, lane, Tl);
+                    screen_tile_split<DC>(Nb, 2 * tp + half, lane, Th, Tl, P16, P16lo, acc);
+                    consume(acc, half);
+                }
+                store(tp);
+            }
+        };
         {
             auto no_store = [](int) {};
             if constexpr (MODE == 1) {
@@ -908,16 +982,13 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             }
         }
         // thresholds: a lane's jsel-th smallest group minimum (negative values,
-        // from rounding, count as 0), as a key.  BF16 mode screens each half of
-        // the landmarks against its own lane's value (each half then holds at
-        // least jsel candidates, 2 jsel >= C in all) and certifies against the
-        // smaller of the two.  FP32 mode (C close to k) takes the larger for
-        // both halves and screens the FP32 keys against it widened by both
-        // error bounds: a landmark counted by a BF16 group minimum has an
-        // exact key at most E16 above it and an FP32 key at most E32 above
-        // that, so each half again holds at least jsel candidates; the
-        // certificate uses the FP32 criterion itself.
-        float tau[2], taucert[2];
+        // from rounding, count as 0), as a key.  The larger of the two lanes'
+        // values, widened by both error bounds, screens both halves in pass 2:
+        // a landmark counted by a BF16 group minimum has an exact key at most
+        // E16 above it and a pass-2 key at most E2 above that, so each half
+        // holds at least jsel candidates (2 jsel >= C in all); the certificate
+        // uses the pass-2 criterion itself.
+        float tbase[2];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
             int v0[16], v1[16];
@@ -931,15 +1002,65 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             int tl = select_jth(v0, v1, a.jsel);
             tl = min(tl, 0x7F7FFFFF);  // +inf (too few landmarks) -> FLT_MAX
             const float own = __int_as_float(tl), oth = __int_as_float(__shfl_xor(tl, 32));
-            if constexpr (MODE == 1) {
-                tau[p] = (own >= FLT_MAX) ? FLT_MAX : own - xnp[p];
-                const float tc = fminf(own, oth);
-                taucert[p] = (tc >= FLT_MAX) ? FLT_MAX : tc - xnp[p];
-            } else {
-                const float tb = fmaxf(own, oth);
-                tau[p] = (tb >= FLT_MAX) ? FLT_MAX : (tb - xnp[p]) + (e16[p] + e32[p]);
-                taucert[p] = tau[p];
+            tbase[p] = fmaxf(own, oth);
+        }
+
+        // Pass-2 operands and their error bound e2.  BF16 mode splits the
+        // point operand as x' = hi + lo + r (hi the pass-1 operand, lo = bf16(x'
+        // - hi), both differences exact in FP32) and the landmark operand as
+        // a = ah + al + ra likewise (from the preparation), and forms ah.hi +
+        // al.hi + ah.lo, three BF16 products per element.  What it leaves out,
+        // a.r - ra.r + al.lo + ra.x', is at most |r| (2 max|L - c| + max|ra|) +
+        // max|al| |lo| + max|ra| |x'|; the FP32 accumulation of three chains of
+        // d_pad products adds (6 d_pad + 16) u (|x'| + max|L - c|)^2 (the
+        // single chain's allowance tripled).  |lo| and |r| are exact per point
+        // (the rows are read again: still in cache).  FP32 mode's FP32 operand
+        // is exact (e32).
+        float e2[2];
+        if constexpr (MODE == 1) {
+            const float la = a.lmax[2], ra = a.lmax[3];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const int64_t pi = pbase + 32 * p + i32;
+                const bool valid = pi < a.n;
+                const float *xr = a.X + (valid ? pi : 0) * a.ldx;
+                float lpart = 0.f, rpart = 0.f;
+#pragma unroll
+                for (int c = 0; c < DC; ++c) {
+                    float v[8];
+                    centred8(a, xr, centL, c, h, valid, v);
+                    unsigned w[4];
+#pragma unroll
+                    for (int e = 0; e < 8; e += 2) {
+                        const float r0 = v[e] - __uint_as_float(bf16_bits_rne(v[e]) << 16);
+                        const float r1 = v[e + 1] - __uint_as_float(bf16_bits_rne(v[e + 1]) << 16);
+                        const unsigned b0 = bf16_bits_rne(r0), b1 = bf16_bits_rne(r1);
+                        const float l0 = __uint_as_float(b0 << 16), l1 = __uint_as_float(b1 << 16);
+                        lpart = fmaf(l0, l0, lpart);
+                        lpart = fmaf(l1, l1, lpart);
+                        rpart = fmaf(r0 - l0, r0 - l0, rpart);
+                        rpart = fmaf(r1 - l1, r1 - l1, rpart);
+                        w[e >> 1] = b0 | (b1 << 16);
+                    }
+                    u32x4 wv = {w[0], w[1], w[2], w[3]};
+                    P16lo.b[p][c] = __builtin_bit_cast(bf16x8, wv);
+                }
+                const float nlo = sqrtf(lpart + __shfl_xor(lpart, 32));
+                const float nr = sqrtf(rpart + __shfl_xor(rpart, 32));
+                const float sx = sqrtf(xnp[p]);
+                const float facc3 = (6.f * DP + 16.f) * U32 * (sx + lmax) * (sx + lmax);
+                e2[p] = 1.01f * (nr * (2.f * lmax + ra) + la * nlo + ra * sx + facc3);
             }
+        } else {
+            e2[0] = e32[0];
+            e2[1] = e32[1];
+        }
+
+        float tau[2], taucert[2];
+#pragma unroll
+        for (int p = 0; p < 2; ++p) {
+            tau[p] = (tbase[p] >= FLT_MAX) ? FLT_MAX : (tbase[p] - xnp[p]) + (e16[p] + e2[p]);
+            taucert[p] = tau[p];
         }
 
         // FP32 mode: the FP32 operand of pass 2 (the rows are still in cache)
@@ -983,9 +1104,9 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             };
             if constexpr (MODE == 1) {
                 if (a.lds_tiles)
-                    screen_pass(BoolTag<true>{}, IntTag<1>{}, P16, a.A, pass2_consume, pass2_store);
+                    screen_pass_split(BoolTag<true>{}, pass2_consume, pass2_store);
                 else
-                    screen_pass(BoolTag<false>{}, IntTag<1>{}, P16, a.A, pass2_consume, pass2_store);
+                    screen_pass_split(BoolTag<false>{}, pass2_consume, pass2_store);
             } else {
                 if (a.lds_tiles)
                     screen_pass(BoolTag<true>{}, IntTag<0>{}, P32, a.A, pass2_consume, pass2_store);
@@ -994,12 +1115,12 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             }
         }
         // Certificate bound per point: a non-candidate's exact distance^2
-        // exceeds tau + |x - c|^2 - E, with E the error bound of the keys pass 2
-        // compared (e16 in BF16 mode, e32 in FP32 mode).
+        // exceeds tau + |x - c|^2 - E, with E = e2 the error bound of the keys
+        // pass 2 compared.
         if (h == 0) {
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                const float E = MODE == 1 ? e16[p] : e32[p];
+                const float E = e2[p];
                 const float tc = taucert[p];
                 float rhs = tc + xnp[p] - E;
                 rhs -= 4.f * U32 * (fabsf(tc) + xnp[p] + E);

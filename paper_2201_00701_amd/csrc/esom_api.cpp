@@ -110,7 +110,7 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg, int64_t 
     sc.prep.norms = static_cast<float *>(take(sizeof(float) * (size_t)ntiles * TILE));
     sc.prep.Lpad = static_cast<float *>(take(sizeof(float) * (size_t)g * dp));
     sc.prep.pairs = pg > 0 ? static_cast<float *>(take(sizeof(float) * (size_t)pg * pg)) : nullptr;
-    sc.prep.lmax = static_cast<float *>(take(2 * sizeof(float)));
+    sc.prep.lmax = static_cast<float *>(take(4 * sizeof(float)));
     sc.prep.perm = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
     sc.prep.ipos = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
     sc.prep.pcl = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
@@ -206,7 +206,7 @@ Plan make_plan(int d, int g, int k, int mode, int candidates) {
     const int maxdc = mode == 1 ? FAST_MAX_DC_BF16 : FAST_MAX_DC_FP32;
     p.fast = p.kp != 0 && p.dc <= maxdc && g <= FAST_MAX_G;
     p.mat = !p.fast && p.kp != 0 && g <= FAST_MAX_G && p.dp <= ESOM_MAX_D;
-    int C = candidates > 0 ? candidates : (mode == 1 ? 2 * k : k + 2);
+    int C = candidates > 0 ? candidates : k + 2;
     if (C < k + 1) C = k + 1;
     p.C = C;
     p.jsel = (C + 1) / 2;
@@ -275,7 +275,7 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
     a.ntiles = pr.ntiles;
     a.npair_tiles = pr.npairs;
     a.A = pr.A;
-    a.A16 = P.mode == ESOM_MODE_BF16_RESCORE ? pr.A : pr.A16;
+    a.A16 = pr.A16;
     a.norms = pr.norms;
     a.cent = pr.cent;
     a.Lpad = pr.Lpad;

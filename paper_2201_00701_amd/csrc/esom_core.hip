@@ -91,6 +91,8 @@ __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
     if (t == 0 && threadIdx.x == 0) {
         lmax[0] = 0.f;
         lmax[1] = 0.f;
+        lmax[2] = 0.f;
+        lmax[3] = 0.f;
         counters[C_FB_LEN] = 0ull;
         counters[C_POINTS] += (unsigned long long)n_points;
     }
@@ -184,12 +186,12 @@ __device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict_
                                int gpad, int d, int dp, int mode, const float *__restrict__ cent,
                                void *__restrict__ A, void *__restrict__ A16, float *__restrict__ norms,
                                float *__restrict__ Lpad, float *__restrict__ lmax, unsigned *wmax) {
-    // wmax: 2 x (waves per block) words of LDS for the block's two maxima
+    // wmax: 4 x (waves per block) words of LDS for the block's four maxima
     const int wv = threadIdx.x >> 6, nw = blockDim.x >> 6;
     const int j = blk * nw + wv;
     const int lane = threadIdx.x & 63;
     if (j >= gpad) {
-        if (lane == 0) wmax[wv] = wmax[nw + wv] = 0u;
+        if (lane == 0) wmax[wv] = wmax[nw + wv] = wmax[2 * nw + wv] = wmax[3 * nw + wv] = 0u;
     } else {
         // Position j sits in tile pair j / 64, screen half j % 2, tile parity
         // (j / 32) % 2 and accumulator register (j / 2) % 16, so that bit b of a
@@ -202,7 +204,10 @@ __device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict_
         const int dc = dp / 16;
         const bool real = j < g;
         const size_t src = real ? (size_t)perm[j] * d : 0;
-        double nrm = 0.0, qe = 0.0;  // |L_j - c|^2, |BF16 quantisation error of -2 (L_j - c)|^2
+        // |L_j - c|^2, |BF16 quantisation error of a = -2 (L_j - c)|^2, and for
+        // the split a = ah + al + ra (ah = bf16(a), al = bf16(a - ah), both
+        // differences exact in FP32) |al|^2 and |ra|^2
+        double nrm = 0.0, qe = 0.0, le = 0.0, re = 0.0;
         for (int q = lane; q < dp; q += 64) {
             const float lv = (real && q < d) ? L[src + q] : 0.f;
             const float c = (real && q < d) ? lv - cent[q] : 0.f;
@@ -211,14 +216,25 @@ __device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict_
             const float a2 = -2.f * c;
             {
                 // A_bf16[t][c][lane = 32 h + m][e], dim = 16 c + 8 h + e: the
-                // BF16 mode's operand, or FP32 mode's threshold-pass operand
+                // BF16 mode's high parts (A) and low parts (A16), or FP32
+                // mode's threshold-pass operand (A16)
                 const int cc = q / 16, hh = (q % 16) / 8, e = q % 8;
+                const size_t at = (((size_t)t * dc + cc) * 64 + 32 * hh + m) * 8 + e;
                 unsigned u = __float_as_uint(a2);
                 u += 0x7FFFu + ((u >> 16) & 1u);
-                const double qd = (double)__uint_as_float(u & 0xFFFF0000u) - (double)a2;
+                const float ah = __uint_as_float(u & 0xFFFF0000u);
+                const double qd = (double)ah - (double)a2;
                 qe += qd * qd;
-                reinterpret_cast<unsigned short *>(mode == 1 ? A : A16)[(((size_t)t * dc + cc) * 64 + 32 * hh + m) * 8 + e] =
-                    (unsigned short)(u >> 16);
+                reinterpret_cast<unsigned short *>(mode == 1 ? A : A16)[at] = (unsigned short)(u >> 16);
+                if (mode == 1) {
+                    const float r1 = a2 - ah;
+                    unsigned v = __float_as_uint(r1);
+                    v += 0x7FFFu + ((v >> 16) & 1u);
+                    const float al = __uint_as_float(v & 0xFFFF0000u);
+                    le += (double)al * (double)al;
+                    re += (double)(r1 - al) * (double)(r1 - al);
+                    reinterpret_cast<unsigned short *>(A16)[at] = (unsigned short)(v >> 16);
+                }
             }
             if (mode == 0) {
                 // A_f32[t][s][lane = 32 h + m], dim = 2 s + h
@@ -230,25 +246,25 @@ __device__ __forceinline__ void prep_landmarks(int blk, const float *__restrict_
         for (int o = 32; o > 0; o >>= 1) {
             nrm += __shfl_xor(nrm, o);
             qe += __shfl_xor(qe, o);
+            le += __shfl_xor(le, o);
+            re += __shfl_xor(re, o);
         }
         if (lane == 0) {
             norms[((size_t)t * 2 + hj) * 16 + rr] = real ? (float)nrm : INFINITY;
             // non-negative floats: integer order is float order
             wmax[wv] = real ? __float_as_uint((float)sqrt(nrm) * 1.0000002f) : 0u;
             wmax[nw + wv] = real ? __float_as_uint((float)sqrt(qe) * 1.0000002f) : 0u;
+            wmax[2 * nw + wv] = real ? __float_as_uint((float)sqrt(le) * 1.0000002f) : 0u;
+            wmax[3 * nw + wv] = real ? __float_as_uint((float)sqrt(re) * 1.0000002f) : 0u;
         }
     }
     // one atomic per block and maximum (the landmark blocks all update the
-    // same two words)
+    // same four words)
     __syncthreads();
-    if (threadIdx.x == 0) {
-        unsigned m0 = 0u, m1 = 0u;
-        for (int w = 0; w < nw; ++w) {
-            m0 = max(m0, wmax[w]);
-            m1 = max(m1, wmax[nw + w]);
-        }
-        if (m0) atomicMax(reinterpret_cast<unsigned *>(lmax), m0);
-        if (m1) atomicMax(reinterpret_cast<unsigned *>(lmax) + 1, m1);
+    if (threadIdx.x < 4) {
+        unsigned mv = 0u;
+        for (int w = 0; w < nw; ++w) mv = max(mv, wmax[threadIdx.x * nw + w]);
+        if (mv) atomicMax(reinterpret_cast<unsigned *>(lmax) + threadIdx.x, mv);
     }
 }
 

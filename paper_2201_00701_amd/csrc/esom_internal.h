@@ -41,12 +41,14 @@ struct Prep {
     int mode = 0;
     int need_pairs = 1;      // 0: the pair table is neither allocated nor filled
     float *cent = nullptr;   // dp      centroid of L (FP32 of an FP64 mean)
-    void *A = nullptr;       // MFMA landmark operand, -2 (L - c), tile layout (the mode's precision)
-    void *A16 = nullptr;     // FP32 mode: the same operand in BF16 (threshold pass); BF16 mode: unused
+    void *A = nullptr;       // MFMA landmark operand a = -2 (L - c), tile layout: FP32 (FP32 mode) or
+                             // its high BF16 parts ah = bf16(a) (BF16 mode)
+    void *A16 = nullptr;     // FP32 mode: bf16(a) (threshold pass); BF16 mode: the low parts bf16(a - ah)
     float *norms = nullptr;  // ntiles * 32: |L_j - c|^2 in MFMA row order
     float *Lpad = nullptr;   // g * dp:  L rows padded with zeros to dp
     float *pairs = nullptr;  // g * g (when need_pairs): 1 / (2 |L_u - L_v|^2), 0 for coincident landmarks
-    float *lmax = nullptr;   // 2:       max_j |L_j - c|, max_j |BF16(-2 (L_j - c)) + 2 (L_j - c)|
+    float *lmax = nullptr;   // 4:       max_j |L_j - c|, max_j |bf16(a_j) - a_j|, and of the split
+                             //          a = ah + al + ra (BF16 mode): max_j |al_j|, max_j |ra_j|
     // Landmark order of the screen tiles, rows and pair table: position ->
     // landmark (perm) and landmark -> position (ipos).  Landmarks that are
     // close in the input space get nearby positions (see prep_order).
@@ -80,7 +82,7 @@ struct EmbedArgs {
     int64_t n, ldx;
     int d, dp, g, ntiles, npair_tiles;
     const void *A;    // screen operand of the candidate pass (BF16 or FP32 by mode)
-    const void *A16;  // BF16 operand of the threshold pass (== A in BF16 mode)
+    const void *A16;  // FP32 mode: BF16 operand of the threshold pass; BF16 mode: low BF16 parts
     const float *norms, *cent, *Lpad, *l2d, *lmax;
     const float *pairs;
     const int32_t *perm, *ipos;  // position -> landmark, landmark -> position

@@ -61,10 +61,15 @@ constexpr float LN_1M_CREFINE = -0.031748698f;  // ln(1 - C_REFINE)
 constexpr int N_REFINE = 4;                      // refined weights per point at most
 
 // Largest block of the fused kernel: 12 waves (3 per SIMD, 168 registers per
-// lane) where the register budget of the instantiation allows it (BF16, padded
-// dimension <= 32, k <= 16), else 8 waves (256 registers).
+// lane) where the register budget of the instantiation allows it (padded
+// dimension <= 32, k <= 16), else 8 waves (256 registers).  In FP32 mode the
+// 12-wave block leaves no LDS room for the FP32 screen tiles (they stream
+// from L2) and spills a few registers once per 64 points, and still runs
+// 8% faster at 1M x 32-D with 400 landmarks than 8 waves with the tiles in
+// LDS: the third wave per SIMD overlaps one wave's MFMA screen with another's
+// VALU phases.
 __host__ __device__ constexpr int main_max_block(int mode, int dc, int kp) {
-    return (mode == 1 && dc <= 2 && kp <= 16) ? 768 : 512;
+    return (dc <= 2 && kp <= 16) ? 768 : 512;
 }
 
 // 1 - exp(z) for z <= 0 with full relative accuracy near 0: Taylor series

@@ -803,9 +803,8 @@ hipError_t launch_embed(const EmbedArgs &a0, int mode, int kp, int num_cus, size
     const size_t wsm = (size_t)wave_smem_bytes(kp, a.k, a.npair_tiles);
     const size_t rows = ((size_t)a.g * (a.dp + 4) * 4 + 255) & ~(size_t)255;
     // Stage the landmark rows in LDS when a full block of waves (one block per
-    // CU: 3 waves per SIMD in BF16 mode, 2 in FP32 mode) still fits beside
-    // them; otherwise rescore from global memory with 4-wave blocks, several
-    // per CU.
+    // CU: 3 or 2 waves per SIMD, main_max_block) still fits beside them;
+    // otherwise rescore from global memory with 4-wave blocks, several per CU.
     // The screen operands (A tiles and norms, read by every wave twice per 64
     // points) join them in LDS when that still fits.
     const int max_wpb = main_max_block(mode, dc, kp) / 64;

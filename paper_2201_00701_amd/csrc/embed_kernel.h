@@ -305,12 +305,12 @@ __host__ __device__ inline size_t tile_lds_bytes(int mode, int ntiles, int dc) {
 }
 
 // Bytes of LDS one wave needs: candidate bitmaps (2 W words per lane), or for
-// KP > 16 the neighbour staging of the pair loop (k entries of 10 bytes per
+// KP > 24 the neighbour staging of the pair loop (k entries of 10 bytes per
 // lane) in the same space; then thresholds, norms and the per-lane masks of
 // non-empty bitmap words.
 __host__ __device__ inline int wave_smem_bytes(int kp, int k, int npair_tiles) {
     const int bits = 2 * npair_tiles * 64 * 4;
-    const int nbr = kp > 16 ? k * 64 * 10 : 0;
+    const int nbr = kp > 24 ? k * 64 * 10 : 0;
     return (bits > nbr ? bits : nbr) + 512 + 1024;
 }
 
@@ -635,8 +635,10 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
         r1 = fmaf(si, ri[1], r1);
     };
     auto run_pairs = [&](auto unit) {
-    if constexpr (KP <= 16) {
-        // neighbour data in registers; each row of pair-table loads is issued
+    if constexpr (KP <= 24) {
+        // neighbour data in registers (fully unrolled: 276 pair slots at
+        // k <= 24, which ran 6% faster at 1M x 48-D, 1024 landmarks, k = 20
+        // than the LDS staging below); each row of pair-table loads is issued
         // together, unconditionally (slots past k hold landmark 0, a valid
         // entry, and are never used), addressed by 32-bit byte offsets from
         // the table base (g <= 4096: under 2^26 bytes)
@@ -663,9 +665,9 @@ __device__ __forceinline__ unsigned project_point(const EmbedArgs &a, const doub
         // larger neighbourhoods: neighbour data through LDS, inner loop unrolled
         // by 4.  The table is symmetric; entry (u, v) is read at row min(u, v),
         // column max(u, v), so a point's reads cover fewer cache lines (each
-        // row only to the right of its own position): 1M x 48-D, 1024
-        // landmarks, k = 20 ran 4% faster.  (With k <= 16 the extra address
-        // arithmetic cost more than it saved.)
+        // row only to the right of its own position): 4% faster at 1M x 48-D,
+        // 1024 landmarks, k = 20 when this path served that shape.  (With
+        // k <= 16 the extra address arithmetic cost more than it saved.)
 #pragma unroll
         for (int q = 0; q < KP; ++q) {
             if (q < a.k) {
@@ -852,7 +854,7 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
     float *nbD2 = reinterpret_cast<float *>(wsm);
     float *nbS = nbD2 + a.k * 64;
     unsigned short *nbI = reinterpret_cast<unsigned short *>(nbS + a.k * 64);
-    const int nbr_bytes = KP > 16 ? a.k * 64 * 10 : 0;
+    const int nbr_bytes = KP > 24 ? a.k * 64 * 10 : 0;
     const int tail = (2 * W * 64 * 4 > nbr_bytes) ? 2 * W * 64 * 4 : nbr_bytes;
     float *certL = reinterpret_cast<float *>(wsm + tail);  // 64 certificate bounds (512 B reserved)
     unsigned long long *maskL = reinterpret_cast<unsigned long long *>(certL + 128);

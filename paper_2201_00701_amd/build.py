@@ -25,7 +25,7 @@ FLAGS = ["-O3", "-std=c++17", "-fPIC", "--offload-arch=" + ARCH,
 UNITS = [("esom_core.hip", []), ("esom_update.hip", []), ("esom_api.cpp", ["-x", "hip"]),
          ("esom_serve.cpp", ["-x", "hip"]), ("esom_som.hip", []), ("esom_graph.hip", []),
          ("esom_embed3.hip", []), ("esom_ablation.hip", []),
-         ("esom_materialise.hip", [])]
+         ("esom_materialise.hip", []), ("esom_bin.hip", [])]
 for mode in (0, 1):
     for kp in (8, 16, 24, 32):
         UNITS.append(("embed_inst.hip", ["-DINST_MODE=%d" % mode, "-DINST_KP=%d" % kp]))

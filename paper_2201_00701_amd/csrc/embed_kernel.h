@@ -339,6 +339,11 @@ __device__ __forceinline__ void centred8(const EmbedArgs &a, const float *xr, co
     }
 }
 
+// Point index of processing slot si < n (the optional locality order).
+__device__ __forceinline__ int64_t slot_point(const EmbedArgs &a, int64_t si) {
+    return a.pt_order ? (int64_t)a.pt_order[si] : si;
+}
+
 template <int MODE, int DC>
 struct PointOperand;
 
@@ -877,9 +882,9 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         float xnp[2], dxp[2];  // |x - c|^2 and |bf16(x - c) - (x - c)|^2
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
-            const int64_t pi = pbase + 32 * p + i32;
-            const bool valid = pi < a.n;
-            const float *xr = a.X + (valid ? pi : 0) * a.ldx;
+            const int64_t si = pbase + 32 * p + i32;
+            const bool valid = si < a.n;
+            const float *xr = a.X + (valid ? slot_point(a, si) : 0) * a.ldx;
             float part = 0.f, dpart = 0.f;
 #pragma unroll
             for (int c = 0; c < DC; ++c) {
@@ -1028,9 +1033,9 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
             const float la = a.lmax[2], ra = a.lmax[3];
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                const int64_t pi = pbase + 32 * p + i32;
-                const bool valid = pi < a.n;
-                const float *xr = a.X + (valid ? pi : 0) * a.ldx;
+                const int64_t si = pbase + 32 * p + i32;
+                const bool valid = si < a.n;
+                const float *xr = a.X + (valid ? slot_point(a, si) : 0) * a.ldx;
                 float lpart = 0.f, rpart = 0.f;
 #pragma unroll
                 for (int c = 0; c < DC; ++c) {
@@ -1075,9 +1080,9 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         if constexpr (MODE == 0) {
 #pragma unroll
             for (int p = 0; p < 2; ++p) {
-                const int64_t pi = pbase + 32 * p + i32;
-                const bool valid = pi < a.n;
-                const float *xr = a.X + (valid ? pi : 0) * a.ldx;
+                const int64_t si = pbase + 32 * p + i32;
+                const bool valid = si < a.n;
+                const float *xr = a.X + (valid ? slot_point(a, si) : 0) * a.ldx;
 #pragma unroll
                 for (int s = 0; s < 8 * DC; ++s) {
                     const int dd = 2 * s + h;
@@ -1144,9 +1149,9 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         __builtin_amdgcn_wave_barrier();
         __builtin_amdgcn_fence(__ATOMIC_ACQUIRE, "wavefront");
 
-        // ---------------- phase B: one lane per point (lane l <-> point pbase + l)
-        const int64_t pi = pbase + lane;
-        const bool valid = pi < a.n;
+        // ---------------- phase B: one lane per point (lane l <-> slot pbase + l)
+        const bool valid = pbase + lane < a.n;
+        const int64_t pi = valid ? slot_point(a, pbase + lane) : 0;  // the point's own index
         const float cert_rhs = certL[lane];
         float x[DP];
         {

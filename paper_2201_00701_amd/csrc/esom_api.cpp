@@ -116,9 +116,14 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg, int64_t 
     sc.prep.pcl = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
     sc.prep.pdist = static_cast<float *>(take(sizeof(float) * (size_t)g));
     sc.prep.ppiv = static_cast<float *>(take(sizeof(float) * 64 * 64));
+    sc.prep.pchain = static_cast<int32_t *>(take(sizeof(int32_t) * 64));
     sc.fb_list = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     sc.fb_reason = static_cast<uint8_t *>(take((size_t)(n > 0 ? n : 1)));
     sc.fb_thresh = static_cast<float *>(take(sizeof(float) * (size_t)(n > 0 ? n : 1)));
+    sc.pt_cell = static_cast<uint8_t *>(take((size_t)(n > 0 ? n : 1)));
+    sc.pt_order = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
+    sc.bin_hist = static_cast<unsigned *>(take(sizeof(unsigned) * 128));
+    sc.prep.bin_hist = sc.bin_hist;
     sc.mat_cap = mat_n;
     if (mat_n > 0) {
         sc.mat_keys = static_cast<float *>(take(sizeof(float) * (size_t)mat_n * ntiles * TILE));
@@ -305,7 +310,7 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
     for (int64_t c0 = 0; c0 < n; c0 += chunk) {
         const int64_t m = n - c0 < chunk ? n - c0 : chunk;
         if (c0 > 0) {
-            e = launch_reset_fallback(counters, s);
+            e = launch_reset_fallback(counters, sc.bin_hist, s);
             if (e != hipSuccess) return hip_fail(e, "counter reset launch");
         }
         a.X = X + c0 * ldx;
@@ -359,6 +364,29 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
             e = launch_fallback(ap, num_cus, lds_per_block, s);
             if (e != hipSuccess) return hip_fail(e, "exact-path launch");
         } else if (pl.fast) {
+            // large landmark sets: the points in locality order (nearest
+            // ordering pivot), so that a wavefront's points share pair-table
+            // lines, landmark rows and candidate words; results are unchanged
+            a.pt_order = nullptr;
+            if (what == EMBED_FULL && g >= BIN_MIN_G && m >= BIN_MIN_N) {
+                BinArgs bb;
+                bb.X = a.X;
+                bb.n = m;
+                bb.ldx = ldx;
+                bb.d = d;
+                bb.dp = pl.dp;
+                bb.g = g;
+                bb.L = L;
+                bb.cent = pr.cent;
+                bb.chain = pr.pchain;
+                bb.hist = sc.bin_hist;
+                bb.cell = sc.pt_cell;
+                bb.order = sc.pt_order;
+                bb.x_vec4 = a.x_vec4;
+                e = launch_bin(bb, num_cus, s);
+                if (e != hipSuccess) return hip_fail(e, "point binning launch");
+                a.pt_order = sc.pt_order;
+            }
             e = launch_embed(a, P.mode, pl.kp, num_cus, lds_per_block, s);
             if (e != hipSuccess) return hip_fail(e, "embed kernel launch");
             if (ev && last) (void)hipEventRecord(ev[2], s);
@@ -637,16 +665,16 @@ int esom_embed_noalloc(const float *X, int64_t n, int32_t d, int64_t ldx, const 
     std::call_once(nd.once, noalloc_setup, std::ref(nd));
     if (nd.err != hipSuccess) return hip_fail(nd.err, "allocation-free scratch set-up");
     // Layout: counters, then the embed scratch for `chunk` points.  Every
-    // chunk point adds 4 + 1 + 4 bytes to the exact-path list; with chunk a
-    // multiple of 256 those three arrays need no alignment padding beyond
-    // what carve reserves for one point each.
+    // chunk point adds 4 + 1 + 4 bytes to the exact-path list and 1 + 4 to
+    // the locality order; with chunk a multiple of 256 those five arrays need
+    // no alignment padding beyond what carve reserves for one point each.
     const Plan pl = make_plan(d, g, P.k, P.mode, P.candidates);
     const int pg = embed_needs_pairs(d, g, P, EMBED_FULL) ? g : 0;
     const size_t room = ESOM_NOALLOC_SCRATCH_BYTES - NOALLOC_COUNTER_BYTES;
     Scratch sc;
     const size_t fixed = carve(sc, nullptr, 1, g, pl.dp, pg);
-    if (fixed + 9 * 256 > room) return fail(ESOM_EINVAL, "landmark set too large for the allocation-free scratch");
-    int64_t chunk = (int64_t)((room - fixed) / 9) & ~(int64_t)255;
+    if (fixed + 14 * 256 > room) return fail(ESOM_EINVAL, "landmark set too large for the allocation-free scratch");
+    int64_t chunk = (int64_t)((room - fixed) / 14) & ~(int64_t)255;
     if (chunk > n) chunk = n;
     if (carve(sc, nullptr, chunk, g, pl.dp, pg) > room)
         return fail(ESOM_EINVAL, "internal: allocation-free scratch layout overflow");

@@ -57,6 +57,8 @@ struct Prep {
     int32_t *pcl = nullptr;   // g: nearest ordering pivot (preparation scratch)
     float *pdist = nullptr;   // g: squared distance to it (preparation scratch)
     float *ppiv = nullptr;    // 64 x 64: pivot-to-pivot squared distances (scratch)
+    int32_t *pchain = nullptr;  // 64: the pivot at each place of the chain
+    unsigned *bin_hist = nullptr;  // the scratch's locality-order counts (zeroed with the counters)
 };
 
 // Scratch memory for one in-flight embed (grows on demand).
@@ -73,6 +75,10 @@ struct Scratch {
     int32_t *mat_idx = nullptr;     // mat_cap x k
     float *mat_d2 = nullptr;        // mat_cap x k
     uint8_t *mat_mark = nullptr;    // mat_cap
+    // locality order of the points (esom_bin.hip), for cap_n points
+    uint8_t *pt_cell = nullptr;     // nearest pivot's place per point
+    int32_t *pt_order = nullptr;    // processing order: slot -> point
+    unsigned *bin_hist = nullptr;   // 2 x 64: points per place, then placement cursors
     unsigned long long *counters = nullptr;  // C_COUNT
     Prep prep;
 };
@@ -111,7 +117,29 @@ struct EmbedArgs {
     // 1: adjacent neighbours FP32 cannot order go to the exact path, so that
     // knn_idx is sorted by exact distance (public calls that return the list)
     int knn_exact_order;
+    // Optional processing order (slot -> point index, a permutation of 0..n-1):
+    // the fused kernel's 64-point tiles take the points of consecutive slots.
+    const int32_t *pt_order;
 };
+
+// Locality order of the points (esom_bin.hip): each point's nearest ordering
+// pivot (BF16 MFMA keys against the 64 pivots), then a counting sort by the
+// pivot's place in the chain.  Used for large landmark sets (g >= BIN_MIN_G)
+// and calls of at least BIN_MIN_N points.
+constexpr int BIN_MIN_G = 512;
+constexpr int64_t BIN_MIN_N = 65536;
+struct BinArgs {
+    const float *X;
+    int64_t n, ldx;
+    int d, dp, g;
+    const float *L, *cent;
+    const int32_t *chain;  // 64: the pivot at each place
+    unsigned *hist;        // 2 x 64, zeroed by the preparation (and per chunk)
+    uint8_t *cell;         // n
+    int32_t *order;        // n
+    int x_vec4;
+};
+hipError_t launch_bin(const BinArgs &b, int num_cus, hipStream_t s);
 
 // Launchers (esom_core.hip).
 hipError_t launch_prep(const Prep &P, const float *L, int mode, unsigned long long *counters,
@@ -121,8 +149,9 @@ hipError_t launch_embed(const EmbedArgs &a, int mode, int kp, int num_cus, size_
 hipError_t launch_fallback(const EmbedArgs &a, int num_cus, size_t lds_per_block, hipStream_t s);
 hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s);
 hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, size_t lds_per_block, hipStream_t s);
-// Resets the fallback-list length (counters[C_FB_LEN]) with a one-thread kernel.
-hipError_t launch_reset_fallback(unsigned long long *counters, hipStream_t s);
+// Resets the fallback-list length (counters[C_FB_LEN]) and the locality-order
+// counts (bin_hist, 128 words, when given) with a one-block kernel.
+hipError_t launch_reset_fallback(unsigned long long *counters, unsigned *bin_hist, hipStream_t s);
 
 // Landmark update (esom_update.hip).
 struct UpdateArgs {

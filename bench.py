@@ -43,9 +43,9 @@ WORKLOADS = {"c2": "c2_fp32_1m", "c3": "c3_bf16_1m", "c4": "c4_large_10m"}
 
 def alu_flops_per_point(g, d, k, cands):
     """Algorithmic VALU work per point of the screened path: one compare per
-    screened key, an exact rescore (subtract, multiply, add) of the rescored
-    candidates, and about 30 flops per active landmark pair (polarised segment
-    projection and the 2x2 accumulation)."""
+    screened key, an exact rescore (subtract, multiply, add) of `cands`
+    candidates (the design's minimum, k + 2), and about 30 flops per active
+    landmark pair (polarised segment projection and the 2x2 accumulation)."""
     return g + 3.0 * cands * d + 30.0 * (k - 1) * (k - 2) / 2.0
 
 
@@ -160,20 +160,24 @@ def roofline_for(mode, n, g, d, k, ms_main, st, workload):
     traffic = measured_traffic(mode, workload)
     if mode == "fp32":
         ach = 2.0 * n * g * d / (ms_main * 1e-3) / 1e12
-        # the screen computes the keys twice (threshold pass and candidate pass)
-        # over the padded landmark and dimension counts
-        issued = 2.0 * 2.0 * n * gpad * dpad / (ms_main * 1e-3) / 1e12
+        # FP32 MFMA runs the candidate pass (the threshold pass is BF16), over
+        # the padded landmark and dimension counts
+        issued = 2.0 * n * gpad * dpad / (ms_main * 1e-3) / 1e12
         return {"bound": "mfma", "achieved": ach, "peak": MFMA_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
                 "frac": ach / MFMA_FP32_PEAK_TFLOPS, "traffic": traffic,
                 "issued_tflops": issued, "issued_frac": issued / MFMA_FP32_PEAK_TFLOPS}
-    cands = max(2 * k, st["n_candidates"] / max(st["n_points"], 1))
-    ach = alu_flops_per_point(g, d, k, 2 * k) * n / (ms_main * 1e-3) / 1e12
+    cands = st["n_candidates"] / max(st["n_points"], 1)
+    ach = alu_flops_per_point(g, d, k, k + 2) * n / (ms_main * 1e-3) / 1e12
     mf = 2.0 * n * g * d / (ms_main * 1e-3) / 1e12
+    # BF16 MFMA issued: the threshold pass and the split candidate pass (three
+    # products per element), over the padded counts
+    mfi = 4.0 * 2.0 * n * gpad * dpad / (ms_main * 1e-3) / 1e12
     return {"bound": "alu", "achieved": ach, "peak": VALU_FP32_PEAK_TFLOPS, "unit": "TFLOP/s",
             "frac": ach / VALU_FP32_PEAK_TFLOPS, "traffic": traffic,
             "peak_nonpacked": VALU_FP32_NONPACKED_TFLOPS,
             "frac_nonpacked": ach / VALU_FP32_NONPACKED_TFLOPS,
             "mfma_bf16_tflops": mf, "mfma_bf16_frac": mf / MFMA_BF16_PEAK_TFLOPS,
+            "mfma_bf16_issued_tflops": mfi, "mfma_bf16_issued_frac": mfi / MFMA_BF16_PEAK_TFLOPS,
             "candidates_per_point": cands}
 
 

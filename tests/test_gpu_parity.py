@@ -485,6 +485,31 @@ def test_non_default_stream_and_determinism(torch_dev, ctx):
     assert torch_dev.equal(a, b) and torch_dev.equal(a, c)
 
 
+@pytest.mark.parametrize("mode", ["bf16", "fp32"])
+def test_locality_order_bit_identical(torch_dev, ctx, oracle_mod, mode):
+    """Calls of at least 65536 points with 512 or more landmarks run their
+    points in locality order (nearest ordering pivot); every point's result
+    depends on nothing but the point, so the outputs must equal, bit for bit,
+    those of calls too small to be reordered, and match the oracle on a
+    sample."""
+    from paper_2201_00701_amd import synth
+    n, d, g, k = 70001, 24, 600, 12
+    X = synth.mixture(n + g, d, 12, seed=77)
+    L = synth.landmarks_from_data(X, g, seed=78)
+    l = synth.grid2d(g, 30)
+    X = np.ascontiguousarray(X[:n])
+    _say("case locality order %s n=%d d=%d g=%d k=%d" % (mode, n, d, g, k))
+    out, idx, d2 = run_case(torch_dev, ctx, X, L, l, k, mode)
+    parts = [run_case(torch_dev, ctx, X[a:a + 30000], L, l, k, mode) for a in range(0, n, 30000)]
+    np.testing.assert_array_equal(out, np.concatenate([p[0] for p in parts]))
+    np.testing.assert_array_equal(idx, np.concatenate([p[1] for p in parts]))
+    np.testing.assert_array_equal(d2, np.concatenate([p[2] for p in parts]))
+    rows = np.random.default_rng(5).choice(n, 1500, replace=False)
+    ref = oracle_mod.embed(X[rows], L, l, k, threads=8)
+    check_parity(X[rows], L, l, k, out[rows], idx[rows], ref, float(np.ptp(l, axis=0).max()),
+                 "locality order %s" % mode)
+
+
 # ---------------------------------------------------------------- landmark update
 
 @pytest.mark.parametrize("kind,sigma", [("kmeans", 0.0), ("som", 1.0), ("som", 0.0)])

@@ -116,14 +116,12 @@ size_t carve(Scratch &sc, void *base, int64_t n, int g, int dp, int pg, int64_t 
     sc.prep.pcl = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)g));
     sc.prep.pdist = static_cast<float *>(take(sizeof(float) * (size_t)g));
     sc.prep.ppiv = static_cast<float *>(take(sizeof(float) * 64 * 64));
-    sc.prep.pchain = static_cast<int32_t *>(take(sizeof(int32_t) * 64));
     sc.fb_list = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     sc.fb_reason = static_cast<uint8_t *>(take((size_t)(n > 0 ? n : 1)));
     sc.fb_thresh = static_cast<float *>(take(sizeof(float) * (size_t)(n > 0 ? n : 1)));
     sc.pt_cell = static_cast<uint8_t *>(take((size_t)(n > 0 ? n : 1)));
     sc.pt_order = static_cast<int32_t *>(take(sizeof(int32_t) * (size_t)(n > 0 ? n : 1)));
     sc.bin_hist = static_cast<unsigned *>(take(sizeof(unsigned) * 128));
-    sc.prep.bin_hist = sc.bin_hist;
     sc.mat_cap = mat_n;
     if (mat_n > 0) {
         sc.mat_keys = static_cast<float *>(take(sizeof(float) * (size_t)mat_n * ntiles * TILE));
@@ -266,6 +264,40 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
     pr.need_pairs = need_pairs ? 1 : 0;
     if (chunk <= 0 || chunk > n) chunk = n;
     if (use_mat && chunk > sc.mat_cap) chunk = sc.mat_cap;
+    // Large landmark sets: the points go through the fused kernel in locality
+    // order (nearest ordering pivot), so that a wavefront's points share
+    // pair-table lines, landmark rows and candidate words; no result changes.
+    // With a second stream and the whole call in one chunk (and no graph
+    // capture on the call's stream) the order is built beside the landmark
+    // preparation; otherwise per chunk on the call's stream.
+    const bool bin_all = pl.fast && what == EMBED_FULL && g >= BIN_MIN_G && n >= BIN_MIN_N;
+    auto bin_args = [&](const float *Xc, int64_t m) {
+        BinArgs bb;
+        bb.X = Xc;
+        bb.n = m;
+        bb.ldx = ldx;
+        bb.d = d;
+        bb.dp = pl.dp;
+        bb.g = g;
+        bb.L = L;
+        bb.hist = sc.bin_hist;
+        bb.cell = sc.pt_cell;
+        bb.order = sc.pt_order;
+        bb.x_vec4 = (d == pl.dp && ldx % 4 == 0 && ((uintptr_t)Xc & 15) == 0) ? 1 : 0;
+        return bb;
+    };
+    bool bin_side = false;
+    if (bin_all && sc.side && chunk >= n) {
+        hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
+        if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+            hipError_t e = hipEventRecord(sc.fork, s);
+            if (e == hipSuccess) e = hipStreamWaitEvent(sc.side, sc.fork, 0);
+            if (e == hipSuccess) e = launch_bin(bin_args(X, n), num_cus, sc.side);
+            if (e == hipSuccess) e = hipEventRecord(sc.join, sc.side);
+            if (e != hipSuccess) return hip_fail(e, "point binning launch");
+            bin_side = true;
+        }
+    }
     if (ev) (void)hipEventRecord(ev[0], s);
     hipError_t e = launch_prep(pr, L, prep_mode, counters, knn_only ? 0 : (long long)n, s);
     if (e != hipSuccess) return hip_fail(e, "landmark preparation launch");
@@ -310,7 +342,7 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
     for (int64_t c0 = 0; c0 < n; c0 += chunk) {
         const int64_t m = n - c0 < chunk ? n - c0 : chunk;
         if (c0 > 0) {
-            e = launch_reset_fallback(counters, sc.bin_hist, s);
+            e = launch_reset_fallback(counters, s);
             if (e != hipSuccess) return hip_fail(e, "counter reset launch");
         }
         a.X = X + c0 * ldx;
@@ -364,26 +396,13 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
             e = launch_fallback(ap, num_cus, lds_per_block, s);
             if (e != hipSuccess) return hip_fail(e, "exact-path launch");
         } else if (pl.fast) {
-            // large landmark sets: the points in locality order (nearest
-            // ordering pivot), so that a wavefront's points share pair-table
-            // lines, landmark rows and candidate words; results are unchanged
             a.pt_order = nullptr;
-            if (what == EMBED_FULL && g >= BIN_MIN_G && m >= BIN_MIN_N) {
-                BinArgs bb;
-                bb.X = a.X;
-                bb.n = m;
-                bb.ldx = ldx;
-                bb.d = d;
-                bb.dp = pl.dp;
-                bb.g = g;
-                bb.L = L;
-                bb.cent = pr.cent;
-                bb.chain = pr.pchain;
-                bb.hist = sc.bin_hist;
-                bb.cell = sc.pt_cell;
-                bb.order = sc.pt_order;
-                bb.x_vec4 = a.x_vec4;
-                e = launch_bin(bb, num_cus, s);
+            if (bin_side) {
+                e = hipStreamWaitEvent(s, sc.join, 0);
+                if (e != hipSuccess) return hip_fail(e, "point binning join");
+                a.pt_order = sc.pt_order;
+            } else if (bin_all && m >= BIN_MIN_N) {
+                e = launch_bin(bin_args(a.X, m), num_cus, s);
                 if (e != hipSuccess) return hip_fail(e, "point binning launch");
                 a.pt_order = sc.pt_order;
             }
@@ -574,6 +593,17 @@ int esom_create(int device, size_t hbm_budget_bytes, esom_ctx **out) {
         delete c;
         return hip_fail(e, "hipMemset");
     }
+    // second stream for the locality order (default priority); without it
+    // the order runs on the call's stream
+    if (hipStreamCreateWithFlags(&c->sc.side, hipStreamNonBlocking) != hipSuccess ||
+        hipEventCreateWithFlags(&c->sc.fork, hipEventDisableTiming) != hipSuccess ||
+        hipEventCreateWithFlags(&c->sc.join, hipEventDisableTiming) != hipSuccess) {
+        (void)hipGetLastError();
+        if (c->sc.fork) (void)hipEventDestroy(c->sc.fork);
+        if (c->sc.side) (void)hipStreamDestroy(c->sc.side);
+        c->sc.side = nullptr;
+        c->sc.fork = c->sc.join = nullptr;
+    }
     *out = c;
     return ESOM_OK;
 }
@@ -623,6 +653,9 @@ void esom_destroy(esom_ctx *c) {
     dev_free(c, reinterpret_cast<void *&>(c->k3idx), c->k3idx_bytes);
     dev_free(c, reinterpret_cast<void *&>(c->lay), c->lay_bytes);
     dev_free(c, reinterpret_cast<void *&>(c->counters), sizeof(unsigned long long) * C_COUNT);
+    if (c->sc.join) (void)hipEventDestroy(c->sc.join);
+    if (c->sc.fork) (void)hipEventDestroy(c->sc.fork);
+    if (c->sc.side) (void)hipStreamDestroy(c->sc.side);
     delete c;
 }
 

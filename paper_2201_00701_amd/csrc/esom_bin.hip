@@ -4,22 +4,24 @@
 // points of a wavefront share: candidate bitmap words, landmark rows and,
 // above all, pair-table lines (g x g entries; 4 MB at g = 1024, which the
 // point stream evicts from L2).  Points in input order share little.  Here
-// every point gets the place (in the landmark preparation's pivot chain) of
-// its nearest ordering pivot, and a counting sort by that place gives the
-// fused kernel its processing order; the outputs still go to the points'
-// own rows.  The order has no effect on any result.
+// every point gets its nearest of 64 ordering pivots (the landmarks j g / 64,
+// the landmark preparation's pivots), and a counting sort by pivot gives the
+// fused kernel its processing order; the outputs still go to the points' own
+// rows.  The order has no effect on any result.  It needs nothing from the
+// landmark preparation, so a context runs it on a second stream beside that.
 //
+//   bin_zero     clears the counts;
 //   bin_keys     one wavefront per 64 points (persistent): the 64 pivots as
-//                a BF16 MFMA A operand (built once per block from L, in LDS),
-//                keys |P_r - c|^2 - 2 <x - c, P_r - c> for both 32-point
-//                halves, the argmin per point (BF16 keys: an approximate
-//                nearest pivot, which is all an order needs), its place into
-//                cell[], and a per-block histogram of places added to hist;
-//   bin_scatter  blocks of BIN_CHUNK points: the block's count per place,
-//                a range per place claimed from the global cursors (offset
-//                by the prefix sum of hist), and each point written to its
-//                slot of order[].  Within a place, slots follow block order
-//                and, inside a block, arrival order.
+//                a BF16 MFMA A operand centred on landmark 0 (built once per
+//                block in LDS), keys |P_i - c0|^2 - 2 <x - c0, P_i - c0> for
+//                both 32-point halves, the argmin per point (BF16 keys: an
+//                approximate nearest pivot, which is all an order needs) into
+//                cell[], and a per-block histogram added to hist;
+//   bin_scatter  blocks of BIN_CHUNK points: the block's count per pivot, a
+//                range per pivot claimed from the global cursors (offset by
+//                the prefix sum of hist), and each point written to its slot
+//                of order[].  Within a pivot, slots follow block order and,
+//                inside a block, arrival order.
 #include <hip/hip_runtime.h>
 #include <stdint.h>
 
@@ -28,14 +30,20 @@
 
 namespace esom {
 
-constexpr int BIN_P = 64;        // ordering pivots (g >= BIN_MIN_G: exactly 64)
+constexpr int BIN_P = 64;        // ordering pivots (g >= BIN_MIN_G)
 constexpr int BIN_WAVES = 4;     // wavefronts per bin_keys block
 constexpr int BIN_CHUNK = 4096;  // points per bin_scatter block
 
+__global__ void bin_zero(unsigned *hist) {
+    if (threadIdx.x < 2 * BIN_P) hist[threadIdx.x] = 0u;
+}
+
 template <int DC>
 __global__ void __launch_bounds__(64 * BIN_WAVES) bin_keys(BinArgs b) {
-    // the pivot operand (2 tiles x DC chunks x 64 lanes) and its norms in
-    // accumulator order ([tile][lane half][16]), built by wavefront 0
+    // the centre (landmark 0, zero past d), the pivot operand (2 tiles x DC
+    // chunks x 64 lanes) and its norms in accumulator order ([tile][lane
+    // half][16])
+    __shared__ float cen[16 * DC];
     __shared__ u32x4 As[2][DC][64];
     __shared__ float Ns[2][2][16];
     __shared__ unsigned hl[BIN_P];
@@ -43,14 +51,14 @@ __global__ void __launch_bounds__(64 * BIN_WAVES) bin_keys(BinArgs b) {
     const int wave = threadIdx.x >> 6;
     const int h = lane >> 5, i32 = lane & 31;
     if (threadIdx.x < BIN_P) hl[threadIdx.x] = 0u;
+    for (int e = threadIdx.x; e < 16 * DC; e += blockDim.x) cen[e] = e < b.d ? b.L[e] : 0.f;
+    __syncthreads();
     if (wave == 0) {
-        // tile t, row m = lane mod 32 is place r = 32 t + m, pivot chain[r],
-        // landmark chain[r] * g / 64 (the preparation's pivot choice); lane l
-        // holds dimensions 16 c + 8 h + e of its row (MFMA A layout)
+        // tile t, row m = lane mod 32 is pivot i = 32 t + m (landmark i g / 64);
+        // lane l holds dimensions 16 c + 8 h + e of its row (MFMA A layout)
 #pragma unroll
         for (int t = 0; t < 2; ++t) {
-            const int r = 32 * t + i32;
-            const int64_t j = ((int64_t)b.chain[r] * b.g) / BIN_P;
+            const int64_t j = ((int64_t)(32 * t + i32) * b.g) / BIN_P;
             const float *Lr = b.L + j * b.d;
             float part = 0.f;
 #pragma unroll
@@ -59,15 +67,15 @@ __global__ void __launch_bounds__(64 * BIN_WAVES) bin_keys(BinArgs b) {
 #pragma unroll
                 for (int e = 0; e < 8; e += 2) {
                     const int q0 = 16 * c + 8 * h + e;
-                    const float v0 = q0 < b.d ? Lr[q0] - b.cent[q0] : 0.f;
-                    const float v1 = q0 + 1 < b.d ? Lr[q0 + 1] - b.cent[q0 + 1] : 0.f;
+                    const float v0 = q0 < b.d ? Lr[q0] - cen[q0] : 0.f;
+                    const float v1 = q0 + 1 < b.d ? Lr[q0 + 1] - cen[q0 + 1] : 0.f;
                     part = fmaf(v0, v0, part);
                     part = fmaf(v1, v1, part);
                     w[e >> 1] = bf16_bits_rne(-2.f * v0) | (bf16_bits_rne(-2.f * v1) << 16);
                 }
                 As[t][c][lane] = u32x4{w[0], w[1], w[2], w[3]};
             }
-            const float nr = part + __shfl_xor(part, 32);  // row m's |P - c|^2 on lanes m, m + 32
+            const float nr = part + __shfl_xor(part, 32);  // row m's |P - c0|^2 on lanes m, m + 32
             // row m sits in lane half (m / 4) % 2, register 4 (m / 8) + m % 4
             if (h == 0) Ns[t][(i32 >> 2) & 1][4 * (i32 >> 3) + (i32 & 3)] = nr;
         }
@@ -88,21 +96,20 @@ __global__ void __launch_bounds__(64 * BIN_WAVES) bin_keys(BinArgs b) {
                 float v[8];
                 if (b.x_vec4) {
                     const float4 *x4 = reinterpret_cast<const float4 *>(xr + 16 * c + 8 * h);
-                    const float4 *c4 = reinterpret_cast<const float4 *>(b.cent + 16 * c + 8 * h);
 #pragma unroll
                     for (int u = 0; u < 2; ++u) {
                         const float4 q = valid ? x4[u] : make_float4(0.f, 0.f, 0.f, 0.f);
-                        const float4 cv = c4[u];
-                        v[4 * u] = q.x - cv.x;
-                        v[4 * u + 1] = q.y - cv.y;
-                        v[4 * u + 2] = q.z - cv.z;
-                        v[4 * u + 3] = q.w - cv.w;
+                        const int q0 = 16 * c + 8 * h + 4 * u;
+                        v[4 * u] = q.x - cen[q0];
+                        v[4 * u + 1] = q.y - cen[q0 + 1];
+                        v[4 * u + 2] = q.z - cen[q0 + 2];
+                        v[4 * u + 3] = q.w - cen[q0 + 3];
                     }
                 } else {
 #pragma unroll
                     for (int e = 0; e < 8; ++e) {
                         const int q = 16 * c + 8 * h + e;
-                        v[e] = (valid && q < b.d) ? xr[q] - b.cent[q] : 0.f;
+                        v[e] = (valid && q < b.d) ? xr[q] - cen[q] : 0.f;
                     }
                 }
                 unsigned w[4];
@@ -199,6 +206,9 @@ static void launch_keys(const BinArgs &b, unsigned blocks, hipStream_t s) {
 }
 
 hipError_t launch_bin(const BinArgs &b, int num_cus, hipStream_t s) {
+    hipLaunchKernelGGL(bin_zero, dim3(1), dim3(2 * BIN_P), 0, s, b.hist);
+    hipError_t e = hipGetLastError();
+    if (e != hipSuccess) return e;
     long long blocks = ((b.n + 63) / 64 + BIN_WAVES - 1) / BIN_WAVES;
     if (blocks > (long long)num_cus * 2) blocks = (long long)num_cus * 2;
     if (blocks < 1) blocks = 1;
@@ -213,7 +223,7 @@ hipError_t launch_bin(const BinArgs &b, int num_cus, hipStream_t s) {
         case 8: launch_keys<8>(b, (unsigned)blocks, s); break;
         default: return hipErrorInvalidValue;
     }
-    hipError_t e = hipGetLastError();
+    e = hipGetLastError();
     if (e != hipSuccess) return e;
     const long long sblocks = (b.n + BIN_CHUNK - 1) / BIN_CHUNK;
     hipLaunchKernelGGL(bin_scatter, dim3((unsigned)(sblocks > 0 ? sblocks : 1)), dim3(256), 0, s, b);

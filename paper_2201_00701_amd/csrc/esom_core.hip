@@ -40,7 +40,7 @@ __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
                               float *__restrict__ cent, float *__restrict__ lmax,
                               unsigned long long *__restrict__ counters, long long n_points,
                               int *__restrict__ pcl, float *__restrict__ pdist,
-                              float *__restrict__ pp, unsigned *__restrict__ bin_hist) {
+                              float *__restrict__ pp) {
     __shared__ double red[256];
     if ((int)blockIdx.x >= dp) {
         // pivot rows staged transposed (dimension-major: lanes read
@@ -88,7 +88,6 @@ __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
         __syncthreads();
     }
     if (threadIdx.x == 0) cent[t] = t < d ? (float)(red[0] / (double)g) : 0.f;
-    if (t == 0 && bin_hist && threadIdx.x < 128) bin_hist[threadIdx.x] = 0u;
     if (t == 0 && threadIdx.x == 0) {
         lmax[0] = 0.f;
         lmax[1] = 0.f;
@@ -106,13 +105,11 @@ __global__ void prep_centroid(const float *__restrict__ L, int g, int d, int dp,
 //  3. a counting sort by place (a histogram and its prefix sum), then each
 //     landmark's position within its place by counting the smaller keys of
 //     the same place only (about g / 64 of them).
-// Writes perm (position -> landmark), ipos (landmark -> position) and chain
-// (the pivot at each place).
+// Writes perm (position -> landmark) and ipos (landmark -> position).
 __global__ void __launch_bounds__(1024) prep_order(int g, const int *__restrict__ pcl,
                                                    const float *__restrict__ pdist,
                                                    const float *__restrict__ ppg,
-                                                   int *__restrict__ perm, int *__restrict__ ipos,
-                                                   int *__restrict__ chain) {
+                                                   int *__restrict__ perm, int *__restrict__ ipos) {
     extern __shared__ __align__(16) unsigned char osm[];
     const int P = order_pivots(g);
     unsigned long long *key = reinterpret_cast<unsigned long long *>(osm);  // g
@@ -135,19 +132,13 @@ __global__ void __launch_bounds__(1024) prep_order(int g, const int *__restrict_
     if (tid < 64) {
         bool taken = tid == 0;
         int cur = 0;
-        if (tid == 0) {
-            place[0] = 0;
-            chain[0] = 0;
-        }
+        if (tid == 0) place[0] = 0;
         for (int r = 1; r < P; ++r) {
             unsigned kv = 0xffffffffu;
             if (tid < P && !taken) kv = (__float_as_uint(fmaxf(pp[cur * P + tid], 0.f)) & ~63u) | (unsigned)tid;
             cur = (int)(__ockl_wfred_min_u32(kv) & 63u);
             if (tid == cur) taken = true;
-            if (tid == 0) {
-                place[cur] = r;
-                chain[r] = cur;
-            }
+            if (tid == 0) place[cur] = r;
         }
     }
     __syncthreads();
@@ -338,11 +329,11 @@ hipError_t launch_prep(const Prep &P, const float *L, int mode,
                        unsigned long long *counters, long long n_points, hipStream_t s) {
     hipLaunchKernelGGL(prep_centroid, dim3(P.dp + (P.g + ASSIGN_PER_BLOCK - 1) / ASSIGN_PER_BLOCK),
                        dim3(256), sizeof(float) * P.d * 64, s, L, P.g, P.d, P.dp, P.cent, P.lmax, counters,
-                       n_points, P.pcl, P.pdist, P.ppiv, P.bin_hist);
+                       n_points, P.pcl, P.pdist, P.ppiv);
     const size_t osm = sizeof(unsigned long long) * P.g + sizeof(float) * ORDER_MAX_P * ORDER_MAX_P +
                        sizeof(int) * (4 * ORDER_MAX_P + P.g);
     hipLaunchKernelGGL(prep_order, dim3(1), dim3(1024), osm, s, P.g, P.pcl, P.pdist, P.ppiv, P.perm,
-                       P.ipos, P.pchain);
+                       P.ipos);
     const int gpad = P.ntiles * TILE;
     const int nlb = (gpad + 3) / 4;
     const int ntu = P.need_pairs ? (P.g + PAIR_TILE - 1) / PAIR_TILE : 0;
@@ -763,13 +754,12 @@ hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, size_t lds_pe
     return hipGetLastError();
 }
 
-__global__ void reset_fallback(unsigned long long *counters, unsigned *bin_hist) {
+__global__ void reset_fallback(unsigned long long *counters) {
     if (threadIdx.x == 0) counters[C_FB_LEN] = 0ull;
-    if (bin_hist && threadIdx.x < 128) bin_hist[threadIdx.x] = 0u;
 }
 
-hipError_t launch_reset_fallback(unsigned long long *counters, unsigned *bin_hist, hipStream_t s) {
-    hipLaunchKernelGGL(reset_fallback, dim3(1), dim3(128), 0, s, counters, bin_hist);
+hipError_t launch_reset_fallback(unsigned long long *counters, hipStream_t s) {
+    hipLaunchKernelGGL(reset_fallback, dim3(1), dim3(64), 0, s, counters);
     return hipGetLastError();
 }
 

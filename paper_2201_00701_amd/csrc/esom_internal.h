@@ -57,8 +57,6 @@ struct Prep {
     int32_t *pcl = nullptr;   // g: nearest ordering pivot (preparation scratch)
     float *pdist = nullptr;   // g: squared distance to it (preparation scratch)
     float *ppiv = nullptr;    // 64 x 64: pivot-to-pivot squared distances (scratch)
-    int32_t *pchain = nullptr;  // 64: the pivot at each place of the chain
-    unsigned *bin_hist = nullptr;  // the scratch's locality-order counts (zeroed with the counters)
 };
 
 // Scratch memory for one in-flight embed (grows on demand).
@@ -78,7 +76,11 @@ struct Scratch {
     // locality order of the points (esom_bin.hip), for cap_n points
     uint8_t *pt_cell = nullptr;     // nearest pivot's place per point
     int32_t *pt_order = nullptr;    // processing order: slot -> point
-    unsigned *bin_hist = nullptr;   // 2 x 64: points per place, then placement cursors
+    unsigned *bin_hist = nullptr;   // 2 x 64: points per pivot, then placement cursors
+    // the locality order runs on a second stream beside the landmark
+    // preparation when the context has one (none: on the call's stream)
+    hipStream_t side = nullptr;
+    hipEvent_t fork = nullptr, join = nullptr;
     unsigned long long *counters = nullptr;  // C_COUNT
     Prep prep;
 };
@@ -122,22 +124,22 @@ struct EmbedArgs {
     const int32_t *pt_order;
 };
 
-// Locality order of the points (esom_bin.hip): each point's nearest ordering
-// pivot (BF16 MFMA keys against the 64 pivots), then a counting sort by the
-// pivot's place in the chain.  Used for large landmark sets (g >= BIN_MIN_G)
-// and calls of at least BIN_MIN_N points.
+// Locality order of the points (esom_bin.hip): each point's nearest of the
+// 64 ordering pivots (landmarks j g / 64, BF16 MFMA keys centred on landmark
+// 0), then a counting sort by pivot.  Needs nothing from the landmark
+// preparation, so it can run beside it.  Used for large landmark sets
+// (g >= BIN_MIN_G) and calls of at least BIN_MIN_N points.
 constexpr int BIN_MIN_G = 512;
 constexpr int64_t BIN_MIN_N = 65536;
 struct BinArgs {
     const float *X;
     int64_t n, ldx;
     int d, dp, g;
-    const float *L, *cent;
-    const int32_t *chain;  // 64: the pivot at each place
-    unsigned *hist;        // 2 x 64, zeroed by the preparation (and per chunk)
+    const float *L;
+    unsigned *hist;        // 2 x 64 (zeroed by launch_bin)
     uint8_t *cell;         // n
     int32_t *order;        // n
-    int x_vec4;
+    int x_vec4;            // 1: d == dp, X 16-byte aligned, ldx % 4 == 0
 };
 hipError_t launch_bin(const BinArgs &b, int num_cus, hipStream_t s);
 
@@ -149,9 +151,8 @@ hipError_t launch_embed(const EmbedArgs &a, int mode, int kp, int num_cus, size_
 hipError_t launch_fallback(const EmbedArgs &a, int num_cus, size_t lds_per_block, hipStream_t s);
 hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s);
 hipError_t launch_all_to_fallback(const EmbedArgs &a, int num_cus, size_t lds_per_block, hipStream_t s);
-// Resets the fallback-list length (counters[C_FB_LEN]) and the locality-order
-// counts (bin_hist, 128 words, when given) with a one-block kernel.
-hipError_t launch_reset_fallback(unsigned long long *counters, unsigned *bin_hist, hipStream_t s);
+// Resets the fallback-list length (counters[C_FB_LEN]) with a one-thread kernel.
+hipError_t launch_reset_fallback(unsigned long long *counters, hipStream_t s);
 
 // Landmark update (esom_update.hip).
 struct UpdateArgs {

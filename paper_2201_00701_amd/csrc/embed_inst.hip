@@ -1,5 +1,6 @@
-// Explicit instantiations of the fused kernel for one (mode, KP) pair.
-// Compiled once per pair with -DINST_MODE=<0|1> -DINST_KP=<8|16|32>.
+// Explicit instantiations of the fused kernel for one (mode, KP, KF) triple.
+// Compiled once per triple with -DINST_MODE=<0|1> -DINST_KP=<8|16|24|32>
+// -DINST_KF=<0|1> (KF = 1: k == KP, k < g).
 #include "embed_kernel.h"
 
 #ifndef INST_MODE
@@ -8,16 +9,20 @@
 #ifndef INST_KP
 #error "INST_KP must be defined"
 #endif
+#ifndef INST_KF
+#error "INST_KF must be defined"
+#endif
 
 #define ESOM_CAT2(a, b, c) a##b##c
-#define ESOM_NAME(m, k) ESOM_CAT2(launch_main_m, m, _kp##k)
-#define ESOM_LAUNCHER(m, k) ESOM_NAME(m, k)
+#define ESOM_NAME(m, k, f) ESOM_CAT2(launch_main_m, m, _kp##k##_kf##f)
+#define ESOM_LAUNCHER(m, k, f) ESOM_NAME(m, k, f)
 
 namespace esom {
 
 template <int MODE, int DC, int KP>
 static hipError_t launch_dc(const EmbedArgs &a, int block, size_t smem, int num_cus, hipStream_t s) {
-    auto kern = a.lds_rows ? embed_main<MODE, DC, KP, 1> : embed_main<MODE, DC, KP, 0>;
+    constexpr int KF = INST_KF;
+    auto kern = a.lds_rows ? embed_main<MODE, DC, KP, 1, KF> : embed_main<MODE, DC, KP, 0, KF>;
     int per_cu = 0;
     if (hipOccupancyMaxActiveBlocksPerMultiprocessor(&per_cu, kern, block, smem) != hipSuccess ||
         per_cu < 1)
@@ -31,8 +36,8 @@ static hipError_t launch_dc(const EmbedArgs &a, int block, size_t smem, int num_
     return hipGetLastError();
 }
 
-hipError_t ESOM_LAUNCHER(INST_MODE, INST_KP)(const EmbedArgs &a, int dc, int block, size_t smem,
-                                             int num_cus, hipStream_t s) {
+hipError_t ESOM_LAUNCHER(INST_MODE, INST_KP, INST_KF)(const EmbedArgs &a, int dc, int block, size_t smem,
+                                                      int num_cus, hipStream_t s) {
     constexpr int M = INST_MODE, K = INST_KP;
     switch (dc) {
         case 1: return launch_dc<M, 1, K>(a, block, smem, num_cus, s);

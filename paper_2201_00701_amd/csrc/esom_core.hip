@@ -787,14 +787,20 @@ hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s
 // Instantiation units (embed_inst.hip, one object per (mode, KP)); each
 // picks the DC instantiation, sizes a persistent grid from the occupancy of
 // that kernel, and launches it.
-hipError_t launch_main_m0_kp8(const EmbedArgs &, int, int, size_t, int, hipStream_t);
-hipError_t launch_main_m0_kp16(const EmbedArgs &, int, int, size_t, int, hipStream_t);
-hipError_t launch_main_m0_kp24(const EmbedArgs &, int, int, size_t, int, hipStream_t);
-hipError_t launch_main_m0_kp32(const EmbedArgs &, int, int, size_t, int, hipStream_t);
-hipError_t launch_main_m1_kp8(const EmbedArgs &, int, int, size_t, int, hipStream_t);
-hipError_t launch_main_m1_kp16(const EmbedArgs &, int, int, size_t, int, hipStream_t);
-hipError_t launch_main_m1_kp24(const EmbedArgs &, int, int, size_t, int, hipStream_t);
-hipError_t launch_main_m1_kp32(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m0_kp8_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m0_kp16_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m0_kp24_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m0_kp32_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m0_kp8_kf1(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m0_kp16_kf1(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m0_kp32_kf1(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m1_kp8_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m1_kp16_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m1_kp24_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m1_kp32_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m1_kp8_kf1(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m1_kp16_kf1(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m1_kp32_kf1(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 
 hipError_t launch_embed(const EmbedArgs &a0, int mode, int kp, int num_cus, size_t lds_per_block,
                         hipStream_t s) {
@@ -824,16 +830,18 @@ hipError_t launch_embed(const EmbedArgs &a0, int mode, int kp, int num_cus, size
     }
     const size_t smem = fixed + (a.lds_rows ? rows : 0) + (a.lds_tiles ? tiles : 0) + (size_t)wpb * wsm;
     const int block = 64 * wpb;
+    // k == KP with k < g has its own instantiation (KP 8, 16 and 32)
+    const bool kf = a.k == kp && a.kact == kp - 1 && kp != 24;
     if (mode == 0) {
-        if (kp == 8) return launch_main_m0_kp8(a, dc, block, smem, num_cus, s);
-        if (kp == 16) return launch_main_m0_kp16(a, dc, block, smem, num_cus, s);
-        if (kp == 24) return launch_main_m0_kp24(a, dc, block, smem, num_cus, s);
-        return launch_main_m0_kp32(a, dc, block, smem, num_cus, s);
+        if (kp == 8) return (kf ? launch_main_m0_kp8_kf1 : launch_main_m0_kp8_kf0)(a, dc, block, smem, num_cus, s);
+        if (kp == 16) return (kf ? launch_main_m0_kp16_kf1 : launch_main_m0_kp16_kf0)(a, dc, block, smem, num_cus, s);
+        if (kp == 24) return launch_main_m0_kp24_kf0(a, dc, block, smem, num_cus, s);
+        return (kf ? launch_main_m0_kp32_kf1 : launch_main_m0_kp32_kf0)(a, dc, block, smem, num_cus, s);
     }
-    if (kp == 8) return launch_main_m1_kp8(a, dc, block, smem, num_cus, s);
-    if (kp == 16) return launch_main_m1_kp16(a, dc, block, smem, num_cus, s);
-    if (kp == 24) return launch_main_m1_kp24(a, dc, block, smem, num_cus, s);
-    return launch_main_m1_kp32(a, dc, block, smem, num_cus, s);
+    if (kp == 8) return (kf ? launch_main_m1_kp8_kf1 : launch_main_m1_kp8_kf0)(a, dc, block, smem, num_cus, s);
+    if (kp == 16) return (kf ? launch_main_m1_kp16_kf1 : launch_main_m1_kp16_kf0)(a, dc, block, smem, num_cus, s);
+    if (kp == 24) return launch_main_m1_kp24_kf0(a, dc, block, smem, num_cus, s);
+    return (kf ? launch_main_m1_kp32_kf1 : launch_main_m1_kp32_kf0)(a, dc, block, smem, num_cus, s);
 }
 
 }  // namespace esom

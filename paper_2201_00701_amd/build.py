@@ -27,7 +27,7 @@ UNITS = [("esom_core.hip", []), ("esom_update.hip", []), ("esom_api.cpp", ["-x",
          ("esom_embed3.hip", []), ("esom_ablation.hip", []),
          ("esom_materialise.hip", []), ("esom_bin.hip", [])]
 for mode in (0, 1):
-    for kp in (8, 16, 24, 32):
+    for kp in (8, 16, 20, 24, 32):
         UNITS.append(("embed_inst.hip", ["-DINST_MODE=%d" % mode, "-DINST_KP=%d" % kp, "-DINST_KF=0"]))
         if kp != 24:
             UNITS.append(("embed_inst.hip", ["-DINST_MODE=%d" % mode, "-DINST_KP=%d" % kp, "-DINST_KF=1"]))

@@ -1,5 +1,5 @@
 // Explicit instantiations of the fused kernel for one (mode, KP, KF) triple.
-// Compiled once per triple with -DINST_MODE=<0|1> -DINST_KP=<8|16|24|32>
+// Compiled once per triple with -DINST_MODE=<0|1> -DINST_KP=<8|16|20|24|32>
 // -DINST_KF=<0|1> (KF = 1: k == KP, k < g).
 #include "embed_kernel.h"
 

@@ -205,7 +205,7 @@ Plan make_plan(int d, int g, int k, int mode, int candidates) {
     Plan p;
     p.dp = 16 * ((d + 15) / 16);
     p.dc = p.dp / 16;
-    p.kp = k <= 8 ? 8 : k <= 16 ? 16 : k <= 24 ? 24 : k <= 32 ? 32 : 0;
+    p.kp = k <= 8 ? 8 : k <= 16 ? 16 : k <= 20 ? 20 : k <= 24 ? 24 : k <= 32 ? 32 : 0;
     const int maxdc = mode == 1 ? FAST_MAX_DC_BF16 : FAST_MAX_DC_FP32;
     p.fast = p.kp != 0 && p.dc <= maxdc && g <= FAST_MAX_G;
     p.mat = !p.fast && p.kp != 0 && g <= FAST_MAX_G && p.dp <= ESOM_MAX_D;

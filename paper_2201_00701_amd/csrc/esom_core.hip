@@ -775,6 +775,8 @@ hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s
         hipLaunchKernelGGL(embed_project<8>, dim3((unsigned)blocks), dim3(block), smem, s, a);
     else if (kp == 16)
         hipLaunchKernelGGL(embed_project<16>, dim3((unsigned)blocks), dim3(block), smem, s, a);
+    else if (kp == 20)
+        hipLaunchKernelGGL(embed_project<20>, dim3((unsigned)blocks), dim3(block), smem, s, a);
     else if (kp == 24)
         hipLaunchKernelGGL(embed_project<24>, dim3((unsigned)blocks), dim3(block), smem, s, a);
     else
@@ -789,6 +791,8 @@ hipError_t launch_project(const EmbedArgs &a, int kp, int num_cus, hipStream_t s
 // that kernel, and launches it.
 hipError_t launch_main_m0_kp8_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m0_kp16_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m0_kp20_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m0_kp20_kf1(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m0_kp24_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m0_kp32_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m0_kp8_kf1(const EmbedArgs &, int, int, size_t, int, hipStream_t);
@@ -796,6 +800,8 @@ hipError_t launch_main_m0_kp16_kf1(const EmbedArgs &, int, int, size_t, int, hip
 hipError_t launch_main_m0_kp32_kf1(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m1_kp8_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m1_kp16_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m1_kp20_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
+hipError_t launch_main_m1_kp20_kf1(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m1_kp24_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m1_kp32_kf0(const EmbedArgs &, int, int, size_t, int, hipStream_t);
 hipError_t launch_main_m1_kp8_kf1(const EmbedArgs &, int, int, size_t, int, hipStream_t);
@@ -830,16 +836,18 @@ hipError_t launch_embed(const EmbedArgs &a0, int mode, int kp, int num_cus, size
     }
     const size_t smem = fixed + (a.lds_rows ? rows : 0) + (a.lds_tiles ? tiles : 0) + (size_t)wpb * wsm;
     const int block = 64 * wpb;
-    // k == KP with k < g has its own instantiation (KP 8, 16 and 32)
+    // k == KP with k < g has its own instantiation (KP 8, 16, 20 and 32)
     const bool kf = a.k == kp && a.kact == kp - 1 && kp != 24;
     if (mode == 0) {
         if (kp == 8) return (kf ? launch_main_m0_kp8_kf1 : launch_main_m0_kp8_kf0)(a, dc, block, smem, num_cus, s);
         if (kp == 16) return (kf ? launch_main_m0_kp16_kf1 : launch_main_m0_kp16_kf0)(a, dc, block, smem, num_cus, s);
+        if (kp == 20) return (kf ? launch_main_m0_kp20_kf1 : launch_main_m0_kp20_kf0)(a, dc, block, smem, num_cus, s);
         if (kp == 24) return launch_main_m0_kp24_kf0(a, dc, block, smem, num_cus, s);
         return (kf ? launch_main_m0_kp32_kf1 : launch_main_m0_kp32_kf0)(a, dc, block, smem, num_cus, s);
     }
     if (kp == 8) return (kf ? launch_main_m1_kp8_kf1 : launch_main_m1_kp8_kf0)(a, dc, block, smem, num_cus, s);
     if (kp == 16) return (kf ? launch_main_m1_kp16_kf1 : launch_main_m1_kp16_kf0)(a, dc, block, smem, num_cus, s);
+    if (kp == 20) return (kf ? launch_main_m1_kp20_kf1 : launch_main_m1_kp20_kf0)(a, dc, block, smem, num_cus, s);
     if (kp == 24) return launch_main_m1_kp24_kf0(a, dc, block, smem, num_cus, s);
     return (kf ? launch_main_m1_kp32_kf1 : launch_main_m1_kp32_kf0)(a, dc, block, smem, num_cus, s);
 }

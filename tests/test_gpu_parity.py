@@ -203,6 +203,13 @@ EDGE = [
     ("g3_k3", 300, 4, 3, 3, "bf16", {}),
     ("g_not_mult64", 800, 12, 197, 16, "bf16", {}),
     ("k32", 600, 16, 300, 32, "bf16", {}),
+    # list sizes and the k == list-size instantiations: k = 18 and 20 (size
+    # 20), 24 (size 24, general), 8 and 16 at k == g - 1 and k == g
+    ("k18_bf16", 900, 40, 500, 18, "bf16", {}),
+    ("k20_fp32", 900, 24, 300, 20, "fp32", {}),
+    ("k24_bf16", 700, 20, 300, 24, "bf16", {}),
+    ("k16_g17", 500, 12, 17, 16, "bf16", {}),
+    ("k8_eq_g", 400, 6, 8, 8, "fp32", {}),
     ("k40_slowpath", 300, 16, 200, 40, "fp32", {}),
     ("d100_bf16", 400, 100, 128, 16, "bf16", {}),
     ("d100_fp32_materialised", 300, 100, 128, 16, "fp32", {}),

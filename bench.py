@@ -39,6 +39,8 @@ VALU_FP32_NONPACKED_TFLOPS = 78.6      # 256 CU x 4 SIMD x 16 lanes x 2.4 GHz x 
 COORD_TOL = 1e-4
 
 WORKLOADS = {"c2": "c2_fp32_1m", "c3": "c3_bf16_1m", "c4": "c4_large_10m"}
+# the tag of each workload's rocprofv3 summaries in profiles/
+PROFILE_TAG = {"c2_fp32_1m": "c2_1m", "c3_bf16_1m": "c3_1m", "c4_large_10m": "c4_10m"}
 
 
 def alu_flops_per_point(g, d, k, cands):
@@ -62,7 +64,7 @@ def measured_traffic(mode, workload):
     """HBM bytes per launch of the fused kernel from the committed rocprofv3
     FETCH_SIZE / WRITE_SIZE summary of this workload, or None when there is
     none or the kernel sources have changed since those counters were taken."""
-    path = os.path.join(ROOT, "profiles", "embed_main_%s_hbm_counters.txt" % workload)
+    path = os.path.join(ROOT, "profiles", "embed_main_%s_hbm_counters.txt" % PROFILE_TAG.get(workload, workload))
     try:
         kv = dict(l.split(": ", 1) for l in open(path).read().splitlines()
                   if ": " in l and not l.startswith("#"))

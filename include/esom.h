@@ -108,7 +108,13 @@ typedef struct {
 void esom_default_params(esom_params *p);
 
 /* Creates a context on HIP device `device`.  hbm_budget_bytes bounds the
- * device memory the context may hold (0 = no bound besides the device). */
+ * device memory the context may hold (0 = no bound besides the device).
+ * The context owns one extra HIP stream (default priority) and two events:
+ * for 512 or more landmarks and 65536 or more points, esom_embed orders the
+ * points for locality on that stream while the landmark preparation runs on
+ * the caller's stream, and joins it before the main kernel (all after the
+ * caller's earlier work on its stream; on the caller's stream itself while
+ * that stream is being captured into a graph). */
 int esom_create(int device, size_t hbm_budget_bytes, esom_ctx **out);
 
 /* Waits for the context's outstanding work and frees everything it owns. */

@@ -451,9 +451,9 @@ def main():
                          "scaling HBM byte counters)")
     args = ap.parse_args()
     if args.gpus != 1:
-        print("bench.py measures one GPU: the projection is data-parallel over points and this "
-              "build runs on a single MI355X (see the sharding design notes); --gpus %d is not "
-              "supported" % args.gpus, file=sys.stderr)
+        print("bench.py measures one GPU: the projection is data-parallel over points, and the "
+              "library runs on a single MI355X (how it would shard is a design note, not code); "
+              "--gpus %d is not supported" % args.gpus, file=sys.stderr)
         sys.exit(2)
 
     import numpy as np

@@ -51,7 +51,7 @@ extern "C" {
 #define ESOM_ETIMEOUT (-5)  /* wait timed out; the request is still pending */
 #define ESOM_ENOTFOUND (-6) /* unknown dataset or request id */
 
-/* Limits of this build. */
+/* Limits of the library. */
 #define ESOM_MAX_D 256   /* high-dimensional point dimension */
 #define ESOM_MAX_K 64    /* neighbours */
 #define ESOM_MAX_G 8192  /* landmarks */

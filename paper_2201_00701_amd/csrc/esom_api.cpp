@@ -289,7 +289,9 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
     bool bin_side = false;
     if (bin_all && sc.side && chunk >= n) {
         hipStreamCaptureStatus cs = hipStreamCaptureStatusNone;
-        if (hipStreamIsCapturing(s, &cs) == hipSuccess && cs == hipStreamCaptureStatusNone) {
+        const hipError_t qe = hipStreamIsCapturing(s, &cs);
+        if (qe != hipSuccess) (void)hipGetLastError();  // unknown: build the order on the call's stream
+        if (qe == hipSuccess && cs == hipStreamCaptureStatusNone) {
             hipError_t e = hipEventRecord(sc.fork, s);
             if (e == hipSuccess) e = hipStreamWaitEvent(sc.side, sc.fork, 0);
             if (e == hipSuccess) e = launch_bin(bin_args(X, n), num_cus, sc.side);

@@ -61,10 +61,14 @@ typedef struct esom_ctx esom_ctx;
 /* Distance pass precision.  Both modes return the exact k-nearest sets (ties
  * broken by landmark index) and the same projection; they differ in how the
  * candidate landmarks are screened:
- *   FP32:          FP32 MFMA distance screen, exact FP32 rescore of candidates;
- *   BF16_RESCORE:  BF16 MFMA screen (FP32 accumulate), exact FP32 rescore of
- *                  at least 2k candidates, certified against a rigorous BF16
- *                  error bound; uncertified points are recomputed exactly. */
+ *   FP32:          BF16 MFMA threshold pass, FP32 MFMA candidate pass, exact
+ *                  FP32 rescore of the candidates;
+ *   BF16_RESCORE:  BF16 MFMA threshold pass, BF16 MFMA candidate pass on split
+ *                  operands (high and low BF16 parts, three products per
+ *                  element, FP32 accumulate), exact FP32 rescore of the
+ *                  candidates.
+ * In both modes every point is certified against a rigorous bound of the
+ * screen's rounding error; uncertified points are recomputed exactly. */
 typedef enum { ESOM_MODE_FP32 = 0, ESOM_MODE_BF16_RESCORE = 1 } esom_mode;
 
 typedef struct {
@@ -79,7 +83,7 @@ typedef struct {
                            system is never singular (default 1e-5) */
     int32_t mode;       /* esom_mode */
     int32_t candidates; /* screen target C (candidates >= C are rescored);
-                           0 = default (k+2 in FP32 mode, 2k in BF16 mode) */
+                           0 = default (k+2) */
 } esom_params;
 
 /* Counters accumulated by a context since creation or the last reset. */

@@ -164,6 +164,62 @@ __device__ __forceinline__ void sort_regs(int (&v)[N]) {
     }
 }
 
+// Bitonic merge of N registers holding a bitonic sequence: ascending after.
+template <int N>
+__device__ __forceinline__ void bitonic_clean(int (&m)[N]) {
+#pragma unroll
+    for (int st = N / 2; st > 0; st >>= 1)
+#pragma unroll
+        for (int i = 0; i < N; ++i)
+            if ((i & st) == 0) {
+                const int x = m[i], y = m[i + st];
+                m[i] = min(x, y);
+                m[i + st] = max(x, y);
+            }
+}
+
+// The j-th smallest (1 <= j <= 32) of the 64 values held by a lane (lo[0..15],
+// hi[0..15]) and its partner lane (lane ^ 32), the same on both lanes.  Each
+// lane orders its own smallest values (16 for j <= 16, else all 32); with two
+// ascending lists s and t of length M, min(s[i], t[M - 1 - i]) holds the M
+// smallest of their union as a bitonic sequence, which a bitonic merge orders.
+// j is uniform.
+__device__ __forceinline__ int select_pair_jth(int (&lo)[16], int (&hi)[16], int j) {
+    if (j <= 16) {
+        sort_regs<16>(lo);
+        sort_regs<16>(hi);
+        int s[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) s[i] = min(lo[i], hi[15 - i]);
+        bitonic_clean<16>(s);
+        int u[16];
+#pragma unroll
+        for (int i = 0; i < 16; ++i) u[i] = min(s[i], __shfl_xor(s[15 - i], 32));
+        bitonic_clean<16>(u);
+        int t = u[0];
+#pragma unroll
+        for (int i = 1; i < 16; ++i)
+            if (i == j - 1) t = u[i];
+        return t;
+    }
+    int v[32];
+#pragma unroll
+    for (int i = 0; i < 16; ++i) {
+        v[i] = lo[i];
+        v[16 + i] = hi[i];
+    }
+    sort_regs<32>(v);
+    int u[32];
+#pragma unroll
+    for (int i = 0; i < 32; ++i) u[i] = min(v[i], __shfl_xor(v[31 - i], 32));
+    bitonic_clean<32>(u);
+    int t = u[31];
+#pragma unroll
+    for (int i = 16; i < 31; ++i)
+        if (i == j - 1) t = u[i];
+    return t;
+}
+
 // The j-th smallest (1 <= j <= 32) of the 32 values lo[0..15], hi[0..15].
 // For j <= 16: with both halves sorted, min(lo[i], hi[15 - i]) holds the 16
 // smallest of the union as a bitonic sequence; its maximum is the 16th
@@ -1000,13 +1056,14 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 screen_pass(BoolTag<false>{}, IntTag<1>{}, P16, a.A16, pass1_consume, no_store);
             }
         }
-        // thresholds: a lane's jsel-th smallest group minimum (negative values,
-        // from rounding, count as 0), as a key.  The larger of the two lanes'
-        // values, widened by both error bounds, screens both halves in pass 2:
-        // a landmark counted by a BF16 group minimum has an exact key at most
-        // E16 above it and a pass-2 key at most E2 above that, so each half
-        // holds at least jsel candidates (2 jsel >= C in all); the certificate
-        // uses the pass-2 criterion itself.
+        // thresholds: the jsel-th smallest of the point's 64 group minima (both
+        // lanes' 32; negative values, from rounding, count as 0), as a key, or
+        // (pair_select = 0, jsel > 32 / 2) the larger of the two lanes' own
+        // jsel-th values.  Widened by both error bounds it screens both halves
+        // in pass 2: the groups are disjoint, and a landmark counted by a BF16
+        // group minimum has an exact key at most E16 above it and a pass-2 key
+        // at most E2 above that, so the point has at least C candidates (jsel,
+        // or 2 jsel); the certificate uses the pass-2 criterion itself.
         float tbase[2];
 #pragma unroll
         for (int p = 0; p < 2; ++p) {
@@ -1018,10 +1075,14 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 v0[r] = max(__float_as_int(gmin[p][0][r] + xnp[p]), 0);
                 v1[r] = max(__float_as_int(gmin[p][1][r] + xnp[p]), 0);
             }
-            int tl = select_jth(v0, v1, a.jsel);
-            tl = min(tl, 0x7F7FFFFF);  // +inf (too few landmarks) -> FLT_MAX
-            const float own = __int_as_float(tl), oth = __int_as_float(__shfl_xor(tl, 32));
-            tbase[p] = fmaxf(own, oth);
+            if (a.pair_select) {
+                const int tl = min(select_pair_jth(v0, v1, a.jsel), 0x7F7FFFFF);  // +inf -> FLT_MAX
+                tbase[p] = __int_as_float(tl);
+            } else {
+                const int tl = min(select_jth(v0, v1, a.jsel), 0x7F7FFFFF);
+                const float own = __int_as_float(tl), oth = __int_as_float(__shfl_xor(tl, 32));
+                tbase[p] = fmaxf(own, oth);
+            }
         }
 
         // Pass-2 operands and their error bound e2.  BF16 mode splits the

@@ -196,7 +196,7 @@ int validate_common(const float *X, int64_t n, int32_t d, int64_t ldx, const flo
 }
 
 struct Plan {
-    int dp, dc, kp, C, jsel;
+    int dp, dc, kp, C, jsel, pair_select;
     bool fast;
     bool mat;  // the materialised-distance path (d beyond the fused kernel's budget)
 };
@@ -209,10 +209,13 @@ Plan make_plan(int d, int g, int k, int mode, int candidates) {
     const int maxdc = mode == 1 ? FAST_MAX_DC_BF16 : FAST_MAX_DC_FP32;
     p.fast = p.kp != 0 && p.dc <= maxdc && g <= FAST_MAX_G;
     p.mat = !p.fast && p.kp != 0 && g <= FAST_MAX_G && p.dp <= ESOM_MAX_D;
-    int C = candidates > 0 ? candidates : k + 2;
-    if (C < k + 1) C = k + 1;
+    int C = candidates > 0 ? candidates : k;
+    if (C < k) C = k;
     p.C = C;
-    p.jsel = (C + 1) / 2;
+    // C <= 32: the C-th of a lane pair's 64 group minima; beyond, each lane's
+    // ceil(C / 2)-th (at most 32), the larger of the two
+    p.pair_select = C <= 32 ? 1 : 0;
+    p.jsel = p.pair_select ? C : (C + 1) / 2;
     if (p.jsel > 32) p.jsel = 32;
     if (p.jsel < 1) p.jsel = 1;
     return p;
@@ -326,6 +329,7 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
     a.k = P.k;
     a.kact = P.k < g ? P.k - 1 : P.k;
     a.jsel = pl.jsel;
+    a.pair_select = pl.pair_select;
     a.use_cutoff = P.k < g ? 1 : 0;
     a.boost = P.boost;
     a.cutoff = P.cutoff;

@@ -94,7 +94,8 @@ struct EmbedArgs {
     const float *norms, *cent, *Lpad, *l2d, *lmax;
     const float *pairs;
     const int32_t *perm, *ipos;  // position -> landmark, landmark -> position
-    int k, kact, jsel;  // kact: neighbours with non-zero score; jsel: per-lane order statistic
+    int k, kact, jsel;  // kact: neighbours with non-zero score; jsel: the screen's order statistic
+    int pair_select;    // 1: jsel-th of a lane pair's 64 group minima; 0: per lane, larger of the two
     int use_cutoff;
     float boost, cutoff, gravity, adjust, Wk;
     float *out;

@@ -220,6 +220,12 @@ EDGE = [
     ("adjust_half", 500, 10, 100, 10, "fp32", {"adjust": 0.5}),
     ("boost_2_gravity0", 500, 10, 100, 10, "bf16", {"boost": 2.0, "gravity": 0.0}),
     ("candidates_k1", 500, 10, 100, 10, "bf16", {"candidates": 11}),
+    # the screen's order statistic: C = k (the default), C = 32 (the largest
+    # over a lane pair's group minima) and C = 40 (per lane, the larger of two)
+    ("candidates_k_fp32", 800, 24, 300, 16, "fp32", {"candidates": 16}),
+    ("candidates_32_bf16", 800, 24, 300, 16, "bf16", {"candidates": 32}),
+    ("candidates_40_bf16", 800, 24, 300, 16, "bf16", {"candidates": 40}),
+    ("candidates_40_k24_fp32", 800, 24, 300, 24, "fp32", {"candidates": 40}),
     # one pair and no gravity: a rank-one system, the centroid on both sides
     ("k3_gravity0", 500, 16, 200, 3, "bf16", {"gravity": 0.0}),
     ("k3_gravity0_slowpath", 64, 63, 4097, 3, "fp32", {"gravity": 0.0}),
@@ -230,7 +236,13 @@ EDGE = [
 def test_edge_cases(torch_dev, ctx, oracle_mod, label, n, d, g, k, mode, extra):
     X, L, l = _problem(_seed(label), n, d, g)
     _say("case edge %s n=%d d=%d g=%d k=%d mode=%s %s" % (label, n, d, g, k, mode, extra))
+    ctx.stats(reset=True)
     out, idx, _ = run_case(torch_dev, ctx, X, L, l, k, mode, **extra)
+    st = ctx.stats(reset=True)
+    if "candidates" in extra:
+        # the screen's guarantee: every point rescores at least C candidates
+        _say("  candidates per point %.2f (C = %d)" % (st["n_candidates"] / n, extra["candidates"]))
+        assert st["n_candidates"] >= min(extra["candidates"], g) * n
     ox = {kk: v for kk, v in extra.items() if kk in ("boost", "adjust", "gravity")}
     ref = oracle_mod.embed(X, L, l, k, threads=8, **ox)
     span = float(max(np.ptp(l[:, 0]), np.ptp(l[:, 1])))

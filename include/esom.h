@@ -82,8 +82,9 @@ typedef struct {
     float gravity;      /* eps >= 0: adds eps*sum_i s_i|p-l_{n_i}|^2 so the 2x2
                            system is never singular (default 1e-5) */
     int32_t mode;       /* esom_mode */
-    int32_t candidates; /* screen target C (candidates >= C are rescored);
-                           0 = default (k+2) */
+    int32_t candidates; /* screen target C: every point rescores at least
+                           min(C, g) candidates; values below k act as k;
+                           0 = default (k) */
 } esom_params;
 
 /* Counters accumulated by a context since creation or the last reset. */

@@ -1043,6 +1043,52 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 store(tp);
             }
         };
+        // BF16 mode's pass 2 for points in locality order: the high product
+        // first, which is the pass-1 key (same operands, same order, error at
+        // most E16).  A 32-point half whose keys of the tile all exceed its
+        // points' tau + E16 + E2 (pass-2 keys then exceed tau) has no candidate
+        // there: the low products are skipped and the tile's bits marked "not
+        // a candidate".  The points of a wavefront share a neighbourhood, and
+        // most tiles hold no candidate of theirs.
+        auto screen_pass_split_skip = [&](auto in_lds, auto consume, auto store, const float (&thr)[2]) {
+            const void *Ab = decltype(in_lds)::value ? static_cast<const void *>(tilesL) : a.A;
+            const float *Nb = decltype(in_lds)::value ? normsL : a.norms;
+            TileRegs<1, DC> Th, Tl;
+            for (int tp = 0; tp < W; ++tp) {
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    const int t = 2 * tp + half;
+                    f32x16 acc[2];
+                    load_tile<1, DC>(Ab, t, lane, Th);
+                    screen_tile<1, DC>(Nb, t, lane, Th, P16, acc);
+                    bool need[2];
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        float m = acc[p][0];
+#pragma unroll
+                        for (int r = 1; r < 16; ++r) m = vmin32(m, acc[p][r], ninf);
+                        need[p] = __ballot(m <= thr[p]) != 0ull;
+                    }
+                    if (need[0] || need[1]) {
+                        load_tile<1, DC>(a.A16, t, lane, Tl);
+#pragma unroll
+                        for (int p = 0; p < 2; ++p) {
+                            if (need[p]) {
+#pragma unroll
+                                for (int c = 0; c < DC; ++c) {
+                                    const bf16x8 al = __builtin_bit_cast(bf16x8, Tl.a[c]);
+                                    const bf16x8 ah = __builtin_bit_cast(bf16x8, Th.a[c]);
+                                    acc[p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(al, P16.b[p][c], acc[p], 0, 0, 0);
+                                    acc[p] = __builtin_amdgcn_mfma_f32_32x32x16_bf16(ah, P16lo.b[p][c], acc[p], 0, 0, 0);
+                                }
+                            }
+                        }
+                    }
+                    consume(acc, need);
+                }
+                store(tp);
+            }
+        };
         {
             auto no_store = [](int) {};
             if constexpr (MODE == 1) {
@@ -1182,11 +1228,37 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                     nonempty[p] |= (unsigned long long)(wd != 0u) << tp;
                 }
             };
+            // a skipped half shifts in 16 "not a candidate" bits
+            auto pass2_consume_skip = [&](const f32x16 (&acc)[2], const bool (&need)[2]) {
+#pragma unroll
+                for (int p = 0; p < 2; ++p) {
+                    if (need[p]) {
+#pragma unroll
+                        for (int r = 0; r < 16; ++r)
+                            word[p] = __builtin_amdgcn_alignbit(word[p], __float_as_uint(tau[p] - acc[p][r]), 31);
+                    } else {
+                        word[p] = (word[p] << 16) | 0xFFFFu;
+                    }
+                }
+            };
             if constexpr (MODE == 1) {
-                if (a.lds_tiles)
+                if (a.pt_order) {
+                    // the skip threshold tau + E16 + E2, rounded up
+                    float thr[2];
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        const float w = e16[p] + e2[p];
+                        thr[p] = (tau[p] + w) + 4.f * U32 * (fabsf(tau[p]) + w);
+                    }
+                    if (a.lds_tiles)
+                        screen_pass_split_skip(BoolTag<true>{}, pass2_consume_skip, pass2_store, thr);
+                    else
+                        screen_pass_split_skip(BoolTag<false>{}, pass2_consume_skip, pass2_store, thr);
+                } else if (a.lds_tiles) {
                     screen_pass_split(BoolTag<true>{}, pass2_consume, pass2_store);
-                else
+                } else {
                     screen_pass_split(BoolTag<false>{}, pass2_consume, pass2_store);
+                }
             } else {
                 if (a.lds_tiles)
                     screen_pass(BoolTag<true>{}, IntTag<0>{}, P32, a.A, pass2_consume, pass2_store);

@@ -1089,6 +1089,55 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                 store(tp);
             }
         };
+        // FP32 mode's pass 2 likewise, for points in locality order: the BF16
+        // key (the pass-1 key, again) decides whether a half needs the tile's
+        // FP32 products.
+        auto screen_pass_fp32_skip = [&](auto in_lds, const auto &P32, auto consume, auto store,
+                                         const float (&thr)[2]) {
+            const void *Ab = decltype(in_lds)::value ? static_cast<const void *>(tilesL) : a.A;
+            const float *Nb = decltype(in_lds)::value ? normsL : a.norms;
+            TileRegs<1, DC> T16;
+            TileRegs<0, DC> T32;
+            for (int tp = 0; tp < W; ++tp) {
+#pragma unroll
+                for (int half = 0; half < 2; ++half) {
+                    const int t = 2 * tp + half;
+                    f32x16 acc[2];
+                    load_tile<1, DC>(a.A16, t, lane, T16);
+                    screen_tile<1, DC>(a.norms, t, lane, T16, P16, acc);
+                    bool need[2];
+#pragma unroll
+                    for (int p = 0; p < 2; ++p) {
+                        float m = acc[p][0];
+#pragma unroll
+                        for (int r = 1; r < 16; ++r) m = vmin32(m, acc[p][r], ninf);
+                        need[p] = __ballot(m <= thr[p]) != 0ull;
+                    }
+                    if (need[0] || need[1]) {
+                        load_tile<0, DC>(Ab, t, lane, T32);
+                        const float4 *np = reinterpret_cast<const float4 *>(Nb + (size_t)(t * 2 + (lane >> 5)) * 16);
+#pragma unroll
+                        for (int p = 0; p < 2; ++p) {
+                            if (need[p]) {
+#pragma unroll
+                                for (int i = 0; i < 4; ++i) {
+                                    const float4 n = np[i];
+                                    acc[p][4 * i] = n.x;
+                                    acc[p][4 * i + 1] = n.y;
+                                    acc[p][4 * i + 2] = n.z;
+                                    acc[p][4 * i + 3] = n.w;
+                                }
+#pragma unroll
+                                for (int s = 0; s < 8 * DC; ++s)
+                                    acc[p] = __builtin_amdgcn_mfma_f32_32x32x2f32(T32.a[s], P32.b[p][s], acc[p], 0, 0, 0);
+                            }
+                        }
+                    }
+                    consume(acc, need);
+                }
+                store(tp);
+            }
+        };
         {
             auto no_store = [](int) {};
             if constexpr (MODE == 1) {
@@ -1241,15 +1290,15 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                     }
                 }
             };
+            // the skip threshold tau + E16 + E2, rounded up
+            float thr[2];
+#pragma unroll
+            for (int p = 0; p < 2; ++p) {
+                const float w = e16[p] + e2[p];
+                thr[p] = (tau[p] + w) + 4.f * U32 * (fabsf(tau[p]) + w);
+            }
             if constexpr (MODE == 1) {
                 if (a.pt_order) {
-                    // the skip threshold tau + E16 + E2, rounded up
-                    float thr[2];
-#pragma unroll
-                    for (int p = 0; p < 2; ++p) {
-                        const float w = e16[p] + e2[p];
-                        thr[p] = (tau[p] + w) + 4.f * U32 * (fabsf(tau[p]) + w);
-                    }
                     if (a.lds_tiles)
                         screen_pass_split_skip(BoolTag<true>{}, pass2_consume_skip, pass2_store, thr);
                     else
@@ -1260,10 +1309,25 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
                     screen_pass_split(BoolTag<false>{}, pass2_consume, pass2_store);
                 }
             } else {
-                if (a.lds_tiles)
-                    screen_pass(BoolTag<true>{}, IntTag<0>{}, P32, a.A, pass2_consume, pass2_store);
-                else
-                    screen_pass(BoolTag<false>{}, IntTag<0>{}, P32, a.A, pass2_consume, pass2_store);
+                // (FP32 mode skips from 48 padded dimensions on, where the FP32
+                // products cost most; below, the BF16 operand is not kept live
+                // through pass 2, which leaves the 12-wave blocks their registers)
+                bool done = false;
+                if constexpr (DC >= 3) {
+                    if (a.pt_order) {
+                        if (a.lds_tiles)
+                            screen_pass_fp32_skip(BoolTag<true>{}, P32, pass2_consume_skip, pass2_store, thr);
+                        else
+                            screen_pass_fp32_skip(BoolTag<false>{}, P32, pass2_consume_skip, pass2_store, thr);
+                        done = true;
+                    }
+                }
+                if (!done) {
+                    if (a.lds_tiles)
+                        screen_pass(BoolTag<true>{}, IntTag<0>{}, P32, a.A, pass2_consume, pass2_store);
+                    else
+                        screen_pass(BoolTag<false>{}, IntTag<0>{}, P32, a.A, pass2_consume, pass2_store);
+                }
             }
         }
         // Certificate bound per point: a non-candidate's exact distance^2

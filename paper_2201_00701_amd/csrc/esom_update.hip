@@ -17,6 +17,7 @@ namespace esom {
 
 constexpr int UPD_BLOCK = 256;
 constexpr int UPD_CHUNK = 4096;  // points per histogram block / per summing chunk
+constexpr int UPD_SCAN = 1024;   // threads of the scan block
 
 // counts[j] += number of points whose nearest landmark is j.
 __global__ void upd_hist(const int32_t *__restrict__ nearest, int64_t ld, int64_t n, int g,
@@ -35,17 +36,53 @@ __global__ void upd_hist(const int32_t *__restrict__ nearest, int64_t ld, int64_
         if (hist[j]) atomicAdd(&counts[j], hist[j]);
 }
 
-// Exclusive scan of counts into offsets[0..g] and cursors (one thread; g is small).
-__global__ void upd_scan(const int *__restrict__ counts, int g, int64_t *__restrict__ offsets,
-                         unsigned long long *__restrict__ cursor) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int64_t run = 0;
-    for (int j = 0; j < g; ++j) {
+// Exclusive scans of the counts (offsets[0..g], cursors) and of the chunks per
+// landmark (ceil(count / UPD_CHUNK)), then the chunk table: chunk c covers
+// [chunk_start, +UPD_CHUNK) of landmark chunk_landmark's range, landmark by
+// landmark.  One block; each thread owns a contiguous run of landmarks.
+__global__ void __launch_bounds__(UPD_SCAN) upd_scan(const int *__restrict__ counts, int g,
+                                                     int64_t *__restrict__ offsets,
+                                                     unsigned long long *__restrict__ cursor,
+                                                     int *__restrict__ chunk_landmark,
+                                                     int *__restrict__ chunk_start, int *__restrict__ nchunks) {
+    __shared__ long long sp[UPD_SCAN];
+    __shared__ int sc[UPD_SCAN];
+    const int per = (g + UPD_SCAN - 1) / UPD_SCAN;
+    const int j0 = threadIdx.x * per, j1 = j0 + per < g ? j0 + per : g;
+    long long pts = 0;
+    int chk = 0;
+    for (int j = j0; j < j1; ++j) {
+        pts += counts[j];
+        chk += (counts[j] + UPD_CHUNK - 1) / UPD_CHUNK;
+    }
+    sp[threadIdx.x] = pts;
+    sc[threadIdx.x] = chk;
+    __syncthreads();
+    // inclusive Hillis-Steele scans of the per-thread totals
+    for (int o = 1; o < UPD_SCAN; o <<= 1) {
+        const long long a = threadIdx.x >= o ? sp[threadIdx.x - o] : 0;
+        const int b = threadIdx.x >= o ? sc[threadIdx.x - o] : 0;
+        __syncthreads();
+        sp[threadIdx.x] += a;
+        sc[threadIdx.x] += b;
+        __syncthreads();
+    }
+    long long run = sp[threadIdx.x] - pts;
+    int c = sc[threadIdx.x] - chk;
+    for (int j = j0; j < j1; ++j) {
         offsets[j] = run;
         cursor[j] = (unsigned long long)run;
         run += counts[j];
+        for (int s0 = 0; s0 < counts[j]; s0 += UPD_CHUNK) {
+            chunk_landmark[c] = j;
+            chunk_start[c] = s0;
+            ++c;
+        }
     }
-    offsets[g] = run;
+    if (threadIdx.x == UPD_SCAN - 1) {
+        offsets[g] = sp[UPD_SCAN - 1];
+        *nchunks = sc[UPD_SCAN - 1];
+    }
 }
 
 // Scatter point indices into their landmark's range.
@@ -117,20 +154,6 @@ __global__ void upd_sum(const float *__restrict__ X, int64_t ldx, int d,
         atomicAdd(&sums[(size_t)j * (d + 1) + t], s);
     }
     if (threadIdx.x == 0) atomicAdd(&sums[(size_t)j * (d + 1) + d], (double)(end - beg));
-}
-
-// Chunk table: chunk c covers [chunk_start, +UPD_CHUNK) of landmark chunk_landmark's range.
-__global__ void upd_chunks(const int *__restrict__ counts, int g, int *__restrict__ chunk_landmark,
-                           int *__restrict__ chunk_start, int *__restrict__ nchunks_out) {
-    if (threadIdx.x != 0 || blockIdx.x != 0) return;
-    int c = 0;
-    for (int j = 0; j < g; ++j)
-        for (int s = 0; s < counts[j]; s += UPD_CHUNK) {
-            chunk_landmark[c] = j;
-            chunk_start[c] = s;
-            ++c;
-        }
-    *nchunks_out = c;
 }
 
 // Blend: one block per landmark j, threads over dimensions.  kind 0: k-means;
@@ -234,13 +257,12 @@ hipError_t launch_update(const UpdateArgs &u, void *ws, int num_cus, hipStream_t
         hipLaunchKernelGGL(upd_hist, dim3(hblocks), dim3(UPD_BLOCK), sizeof(int) * u.g, s, u.nearest,
                            u.nearest_ld, u.n, u.g, counts);
     }
-    hipLaunchKernelGGL(upd_scan, dim3(1), dim3(64), 0, s, counts, u.g, offsets, cursor);
+    hipLaunchKernelGGL(upd_scan, dim3(1), dim3(UPD_SCAN), 0, s, counts, u.g, offsets, cursor,
+                       chunk_landmark, chunk_start, nchunks);
     if (u.n > 0) {
         const size_t sh = sizeof(int) * 2 * (size_t)u.g + sizeof(long long) * (size_t)u.g;
         hipLaunchKernelGGL(upd_scatter, dim3(hblocks), dim3(UPD_BLOCK), sh, s, u.nearest, u.nearest_ld,
                            u.n, u.g, cursor, perm);
-        hipLaunchKernelGGL(upd_chunks, dim3(1), dim3(64), 0, s, counts, u.g, chunk_landmark,
-                           chunk_start, nchunks);
         // Grid sized for the worst case; blocks past the chunk count exit at once.
         hipLaunchKernelGGL(upd_sum, dim3((unsigned)maxchunks), dim3(UPD_BLOCK), 0, s, u.X, u.ldx,
                            u.d, perm, offsets, chunk_landmark, chunk_start, nchunks, sums);

@@ -103,7 +103,8 @@ typedef struct {
                               shape is outside the fast kernels (k > 32, d above
                               the mode's fast limit, or g > 4096) */
     int64_t n_timed;       /* embed calls timed (see esom_set_timing) */
-    double ms_prep;        /* summed device time of landmark preparation */
+    double ms_prep;        /* summed device time of landmark preparation (and of
+                              the points' locality order where it outlasts it) */
     double ms_main;        /* summed device time of the fused embed kernel */
     double ms_exact;       /* summed device time of the exact FP64 path */
 } esom_stats;
@@ -376,7 +377,8 @@ int esom_get_fallback(esom_ctx *ctx, void *stream, int32_t *points, uint8_t *rea
 /* enable != 0: every following esom_embed on this context records HIP events
  * on its stream around the landmark preparation, the fused kernel and the
  * exact path; esom_get_stats adds their elapsed times to ms_prep / ms_main /
- * ms_exact.  Timing serialises nothing but costs six event records per call. */
+ * ms_exact.  Timing serialises nothing but costs four or five event records
+ * per call. */
 int esom_set_timing(esom_ctx *ctx, int32_t enable);
 
 /* ---------------------------------------------------------------- serving

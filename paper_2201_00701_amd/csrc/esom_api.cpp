@@ -407,6 +407,10 @@ int enqueue_embed(Scratch &sc, unsigned long long *counters, int num_cus, size_t
                 e = hipStreamWaitEvent(s, sc.join, 0);
                 if (e != hipSuccess) return hip_fail(e, "point binning join");
                 a.pt_order = sc.pt_order;
+                // the fused kernel's timing starts after the join: whatever of
+                // the locality order outlasts the landmark preparation counts
+                // as preparation
+                if (ev) (void)hipEventRecord(ev[1], s);
             } else if (bin_all && m >= BIN_MIN_N) {
                 e = launch_bin(bin_args(a.X, m), num_cus, s);
                 if (e != hipSuccess) return hip_fail(e, "point binning launch");

@@ -1153,8 +1153,8 @@ __global__ void __launch_bounds__(main_max_block(MODE, DC, KP)) embed_main(Embed
         }
         // thresholds: the jsel-th smallest of the point's 64 group minima (both
         // lanes' 32; negative values, from rounding, count as 0), as a key, or
-        // (pair_select = 0, jsel > 32 / 2) the larger of the two lanes' own
-        // jsel-th values.  Widened by both error bounds it screens both halves
+        // (pair_select = 0: C above 32, jsel = ceil(C / 2)) the larger of the
+        // two lanes' own jsel-th values.  Widened by both error bounds it screens both halves
         // in pass 2: the groups are disjoint, and a landmark counted by a BF16
         // group minimum has an exact key at most E16 above it and a pass-2 key
         // at most E2 above that, so the point has at least C candidates (jsel,
